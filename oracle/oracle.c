@@ -1,0 +1,492 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow CPU FP64 reference for the potential of charges in a layered
+ * medium (Wang, Zhang & Cai, "Fast multipole method for 3-D Laplace equation
+ * in layered media", arXiv:1908.10863).  Only tests/, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this file's library.  It shares
+ * no code with the GPU path.
+ *
+ * What is computed (Sec. 3.1, eqs. totalinteraction / freereactioncomponents):
+ *   Phi_i = sum_{j != i, same layer} q_j / (4 pi |r_i - r_j|)
+ *         + sum_{j (all, incl. j = i)} q_j sum_{valid ab} u^{ab}(r_i, r_j)
+ *   u^{ab}(r, r') = 1/(4 pi) int_0^inf J0(k rho) exp(-k zeta^{ab}) sigma^{ab}(k) dk
+ * with zeta^{ab} the interface-relative exponent of eq. zexponential and the
+ * 1/(8 pi^2) double integral of eq. generalcomponents reduced to J0 by the
+ * Bessel integral of Sec. 3.4.
+ *
+ * Conventions (layer l is d_l < z < d_{l-1}; layer 0 on top, layer L at the
+ * bottom; interfaces d_0 > d_1 > ... > d_{L-1}):
+ *   a = 1 : target-side wave from the target layer's bottom interface d_l
+ *   a = 2 : target-side wave from its top interface d_{l-1}
+ *   b = 1 : source wave towards the source layer's bottom interface d_l'
+ *   b = 2 : source wave towards its top interface d_{l'-1}
+ * Output arrays of four sigmas are indexed [2*(a-1) + (b-1)].
+ *
+ * Parity pins for every function live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+#define OR_MAXL 16
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+static int valid_side(int L, int layer, int side) {
+  return side == 1 ? (layer <= L - 1) : (layer >= 1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reaction densities by a direct solve of the interface system (App. A).    */
+/*                                                                          */
+/* In layer i the reaction part of the transformed field (normalised by the  */
+/* free-space factor) is  s1_i exp(-k(z - d_i)) + s2_i exp(-k(d_{i-1} - z)), */
+/* with s2_0 = s1_L = 0 for decay at +-infinity.  The source's own free wave */
+/* reaches its bottom interface with amplitude g1 and its top one with g2.   */
+/* Continuity of u and eps du/dz at every interface d_i gives 2L equations   */
+/* for the 2L unknowns; b = 1 is the response to (g1,g2) = (1,0) and b = 2   */
+/* the response to (0,1).  Gaussian elimination with partial pivoting.       */
+/* ------------------------------------------------------------------------ */
+int oracle_sigma(int L, const double* d, const double* eps, int lt, int ls,
+                 double k, double* out) {
+  if (L < 1 || L > OR_MAXL || lt < 0 || lt > L || ls < 0 || ls > L) return -1;
+  const int n = 2 * L;
+  double A[2 * OR_MAXL][2 * OR_MAXL];
+  double R[2 * OR_MAXL][2];
+  memset(A, 0, sizeof(A));
+  memset(R, 0, sizeof(R));
+  /* unknown columns: s1_i (i = 0..L-1) -> i ; s2_i (i = 1..L) -> L + i - 1 */
+#define C1(i) (i)
+#define C2(i) (L + (i) - 1)
+  for (int i = 0; i < L; ++i) {
+    /* e_i = exp(-k D_i), D_i = d_{i-1} - d_i : thickness of layer i (i >= 1) */
+    const double ei = (i >= 1) ? exp(-k * (d[i - 1] - d[i])) : 0.0;
+    const double ei1 = (i + 1 <= L - 1) ? exp(-k * (d[i] - d[i + 1])) : 0.0;
+    const int rc = 2 * i, rf = 2 * i + 1;
+    /* continuity of u at z = d_i */
+    A[rc][C1(i)] += 1.0;
+    if (i >= 1) A[rc][C2(i)] += ei;
+    if (i + 1 <= L - 1) A[rc][C1(i + 1)] -= ei1;
+    A[rc][C2(i + 1)] -= 1.0;
+    if (ls == i) R[rc][0] -= 1.0;     /* g1 on the upper side */
+    if (ls == i + 1) R[rc][1] += 1.0; /* g2 on the lower side */
+    /* continuity of eps du/dz at z = d_i (divided by -k) */
+    A[rf][C1(i)] += eps[i];
+    if (i >= 1) A[rf][C2(i)] -= eps[i] * ei;
+    if (i + 1 <= L - 1) A[rf][C1(i + 1)] -= eps[i + 1] * ei1;
+    A[rf][C2(i + 1)] += eps[i + 1];
+    if (ls == i) R[rf][0] += eps[i];
+    if (ls == i + 1) R[rf][1] += eps[i + 1];
+  }
+  /* elimination with partial pivoting */
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (A[piv][c] == 0.0) return -2;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) { double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
+      for (int j = 0; j < 2; ++j) { double t = R[c][j]; R[c][j] = R[piv][j]; R[piv][j] = t; }
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r][c] / A[c][c];
+      if (f == 0.0) continue;
+      for (int j = c; j < n; ++j) A[r][j] -= f * A[c][j];
+      R[r][0] -= f * R[c][0];
+      R[r][1] -= f * R[c][1];
+    }
+  }
+  double X[2 * OR_MAXL][2];
+  for (int c = n - 1; c >= 0; --c) {
+    for (int j = 0; j < 2; ++j) {
+      double s = R[c][j];
+      for (int m = c + 1; m < n; ++m) s -= A[c][m] * X[m][j];
+      X[c][j] = s / A[c][c];
+    }
+  }
+  for (int a = 1; a <= 2; ++a)
+    for (int b = 1; b <= 2; ++b) {
+      double v = 0.0;
+      if (valid_side(L, lt, a) && valid_side(L, ls, b)) {
+        const int col = (a == 1) ? C1(lt) : C2(lt);
+        v = X[col][b - 1];
+      }
+      out[2 * (a - 1) + (b - 1)] = v;
+    }
+#undef C1
+#undef C2
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closed-form densities of a three-layer medium (App. A, eqs.               */
+/* densitythreelayer1-3), written with x = exp(-k D), D = d_0 - d_1, as      */
+/* sigma = (n0 + n1 x + n2 x^2) / (2 kappa),                                 */
+/* kappa = [(e0+e1)(e1+e2) + (e0-e1)(e1-e2) x^2] / 2.                        */
+/* Two printed entries are read differently (see the reading list kept with  */
+/* the design notes): the x^2 term of kappa carries (e1 - e2) and the two    */
+/* numerator terms of sigma^{22}_{22} pair as (e2-e1)(e0+e1) + (e1-e0)(e1+e2)x^2, */
+/* so that every density tends to its nearest-interface limit as k -> inf.   */
+/* ------------------------------------------------------------------------ */
+static void sigma3_numerators(const double* e, int lt, int ls, int a, int b,
+                              double* n0, double* n1, double* n2) {
+  const double e0 = e[0], e1 = e[1], e2 = e[2];
+  *n0 = *n1 = *n2 = 0.0;
+  const int code = lt * 1000 + ls * 100 + a * 10 + b;
+  switch (code) {
+    /* source in the top layer */
+    case 11: *n0 = (e0 - e1) * (e1 + e2); *n2 = (e0 + e1) * (e1 - e2); break; /* s^{11}_{00} */
+    case 1021: *n0 = 2.0 * e0 * (e1 + e2); break;                              /* s^{21}_{10} */
+    case 1011: *n1 = 2.0 * e0 * (e1 - e2); break;                              /* s^{11}_{10} */
+    case 2021: *n1 = 4.0 * e0 * e1; break;                                     /* s^{21}_{20} */
+    /* source in the middle layer */
+    case 112: *n0 = 2.0 * e1 * (e1 + e2); break;                               /* s^{12}_{01} */
+    case 111: *n1 = 2.0 * e1 * (e1 - e2); break;                               /* s^{11}_{01} */
+    case 1111: *n0 = (e1 - e2) * (e1 + e0); break;                             /* s^{11}_{11} */
+    case 1121: *n1 = (e1 - e2) * (e1 - e0); break;                             /* s^{21}_{11} */
+    case 1112: *n1 = (e1 - e2) * (e1 - e0); break;                             /* s^{12}_{11} */
+    case 1122: *n0 = (e1 + e2) * (e1 - e0); break;                             /* s^{22}_{11} */
+    case 2122: *n1 = 2.0 * e1 * (e1 - e0); break;                              /* s^{22}_{21} */
+    case 2121: *n0 = 2.0 * e1 * (e0 + e1); break;                              /* s^{21}_{21} */
+    /* source in the bottom layer */
+    case 212: *n1 = 4.0 * e1 * e2; break;                                      /* s^{12}_{02} */
+    case 1222: *n1 = 2.0 * e2 * (e1 - e0); break;                              /* s^{22}_{12} */
+    case 1212: *n0 = 2.0 * e2 * (e0 + e1); break;                              /* s^{12}_{12} */
+    case 2222: *n0 = (e2 - e1) * (e0 + e1); *n2 = (e1 - e0) * (e1 + e2); break; /* s^{22}_{22} */
+    default: break;
+  }
+}
+
+int oracle_sigma3(const double* d, const double* eps, int lt, int ls, double k,
+                  double* out) {
+  if (lt < 0 || lt > 2 || ls < 0 || ls > 2) return -1;
+  const double x = exp(-k * (d[0] - d[1]));
+  const double kap = 0.5 * ((eps[0] + eps[1]) * (eps[1] + eps[2]) +
+                            (eps[0] - eps[1]) * (eps[1] - eps[2]) * x * x);
+  for (int a = 1; a <= 2; ++a)
+    for (int b = 1; b <= 2; ++b) {
+      double n0, n1, n2;
+      sigma3_numerators(eps, lt, ls, a, b, &n0, &n1, &n2);
+      out[2 * (a - 1) + (b - 1)] = (n0 + n1 * x + n2 * x * x) / (2.0 * kap);
+    }
+  return 0;
+}
+
+/* Image series of a three-layer density: expanding 1/kappa as a geometric    */
+/* series in x^2 gives sigma(k) = sum_t c_t exp(-k s_t D) with s_t integer,   */
+/* hence u^{ab} = sum_t c_t / (4 pi sqrt(rho^2 + (zeta + s_t D)^2)).          */
+/* Fills up to maxterm (coef, shift) pairs; returns the count.                */
+int oracle_image3_terms(const double* eps, int lt, int ls, int a, int b,
+                        int maxterm, double* coef, int* shift) {
+  double n0, n1, n2;
+  sigma3_numerators(eps, lt, ls, a, b, &n0, &n1, &n2);
+  const double P = (eps[0] + eps[1]) * (eps[1] + eps[2]);
+  const double Rr = (eps[0] - eps[1]) * (eps[1] - eps[2]);
+  const double ratio = -Rr / P; /* 1/kappa = (2/P) sum_j ratio^j x^{2j} */
+  /* sigma = (1/P) sum_j ratio^j (n0 x^{2j} + n1 x^{2j+1} + n2 x^{2j+2}) */
+  int cnt = 0;
+  double rj = 1.0;
+  for (int j = 0; j < 400 && cnt + 3 <= maxterm; ++j) {
+    const double mag = fabs(rj) * (fabs(n0) + fabs(n1) + fabs(n2)) / P;
+    if (j > 0 && mag < 1e-19) break;
+    if (n0 != 0.0) { coef[cnt] = rj * n0 / P; shift[cnt] = 2 * j; ++cnt; }
+    if (n1 != 0.0) { coef[cnt] = rj * n1 / P; shift[cnt] = 2 * j + 1; ++cnt; }
+    if (n2 != 0.0) { coef[cnt] = rj * n2 / P; shift[cnt] = 2 * j + 2; ++cnt; }
+    rj *= ratio;
+    if (rj == 0.0) break;
+  }
+  return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed composite Gauss-Legendre rule on [0, kmax] for the Sommerfeld       */
+/* integrals.  Nodes are shared by every pair of one call so that sigma(k)   */
+/* is evaluated once per node.  A density is a sum of exponentials           */
+/* exp(-c k) (multiple reflections in the finite layers), so panels start    */
+/* small at k = 0 and grow geometrically (ratio 1.2, width ~ k/5): any       */
+/* exponential is then integrated to full precision where it is not         */
+/* negligible.  The panel width is capped so that 20 points cover at most a  */
+/* full period of J0(k rho_max), ten e-folds of exp(-k zeta_min) and a tenth */
+/* of the multiple-reflection scale of the thinnest finite layer.            */
+/* ------------------------------------------------------------------------ */
+#define GL_NPT 20
+static void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double t = cos(OR_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      /* p1 = P_n(t), p0 = P_{n-1}(t) */
+      double dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+typedef struct {
+  int nn;
+  double* k;
+  double* w;
+} rule_t;
+
+static int make_rule(double rho_max, double zeta_min, double dmin, rule_t* r) {
+  double gx[GL_NPT], gw[GL_NPT];
+  gauss_legendre(GL_NPT, gx, gw);
+  const double kmax = 45.0 / zeta_min;
+  double hmax = 10.0 / zeta_min;
+  if (rho_max > 0.0 && 2.0 * OR_PI / rho_max < hmax) hmax = 2.0 * OR_PI / rho_max;
+  if (dmin > 0.0 && 5.0 * dmin < hmax) hmax = 5.0 * dmin;
+  double scale = zeta_min < 1.0 ? zeta_min : 1.0;
+  if (dmin > 0.0 && dmin < scale) scale = dmin;
+  const double h0 = 1e-3 * scale;
+  /* count panels */
+  int npan = 0;
+  for (double k0 = 0.0, h = h0; k0 < kmax; ++npan) {
+    k0 += h;
+    h = (h * 1.2 < hmax) ? h * 1.2 : hmax;
+  }
+  r->nn = npan * GL_NPT;
+  r->k = (double*)malloc(sizeof(double) * r->nn);
+  r->w = (double*)malloc(sizeof(double) * r->nn);
+  if (!r->k || !r->w) return -1;
+  double k0 = 0.0, h = h0;
+  for (int p = 0; p < npan; ++p) {
+    for (int i = 0; i < GL_NPT; ++i) {
+      r->k[p * GL_NPT + i] = k0 + 0.5 * h * (gx[i] + 1.0);
+      r->w[p * GL_NPT + i] = 0.5 * h * gw[i];
+    }
+    k0 += h;
+    h = (h * 1.2 < hmax) ? h * 1.2 : hmax;
+  }
+  return 0;
+}
+
+/* smallest thickness of a finite layer, 0 when there is none */
+static double min_thickness(int L, const double* d) {
+  double m = 0.0;
+  for (int i = 1; i < L; ++i) {
+    const double t = d[i - 1] - d[i];
+    if (m == 0.0 || t < m) m = t;
+  }
+  return m;
+}
+
+static void free_rule(rule_t* r) {
+  free(r->k);
+  free(r->w);
+}
+
+/* One reaction component by quadrature: 1/(4pi) int J0(k rho) e^{-k zeta} sigma dk.
+ * sigma from the direct solve (or sigma == 1 when L == 0). */
+double oracle_reaction_quad(int L, const double* d, const double* eps, int lt,
+                            int ls, int a, int b, double rho, double zeta) {
+  rule_t r;
+  if (make_rule(rho, zeta, L > 0 ? min_thickness(L, d) : 0.0, &r)) return NAN;
+  double acc = 0.0, cmp = 0.0;
+  for (int i = 0; i < r.nn; ++i) {
+    double sg = 1.0;
+    if (L > 0) {
+      double s4[4];
+      oracle_sigma(L, d, eps, lt, ls, r.k[i], s4);
+      sg = s4[2 * (a - 1) + (b - 1)];
+    }
+    const double f = r.w[i] * j0(r.k[i] * rho) * exp(-r.k[i] * zeta) * sg;
+    /* Neumaier summation */
+    const double t = acc + f;
+    if (fabs(acc) >= fabs(f)) cmp += (acc - t) + f; else cmp += (f - t) + acc;
+    acc = t;
+  }
+  free_rule(&r);
+  return (acc + cmp) / (4.0 * OR_PI);
+}
+
+double oracle_reaction_image3(const double* d, const double* eps, int lt, int ls,
+                              int a, int b, double rho, double zeta) {
+  double coef[1200];
+  int shift[1200];
+  const int nt = oracle_image3_terms(eps, lt, ls, a, b, 1200, coef, shift);
+  const double D = d[0] - d[1];
+  double acc = 0.0;
+  for (int t = nt - 1; t >= 0; --t) {
+    const double zz = zeta + shift[t] * D;
+    acc += coef[t] / sqrt(rho * rho + zz * zz);
+  }
+  return acc / (4.0 * OR_PI);
+}
+
+/* exponent zeta^{ab} of eq. zexponential (interface-relative distances) */
+static double zeta_of(const double* d, int lt, int ls, int a, int b, double z,
+                      double zs) {
+  const double t = (a == 1) ? (z - d[lt]) : (d[lt - 1] - z);
+  const double s = (b == 1) ? (zs - d[ls]) : (d[ls - 1] - zs);
+  return t + s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct potential at selected targets.                                     */
+/*   method 0: reaction kernels by quadrature (any number of layers)         */
+/*   method 1: reaction kernels by the three-layer image series (L == 2)     */
+/*   parts   : bit 0 free space, bit 1 reaction                              */
+/* Targets are indices into the N points; phi_out has nt entries.            */
+/* ------------------------------------------------------------------------ */
+int oracle_potential(int L, const double* d, const double* eps, int64_t n,
+                     const double* x, const double* y, const double* z,
+                     const int32_t* layer, const double* q, int64_t nt,
+                     const int64_t* targets, int method, int parts,
+                     double* phi_out) {
+  if (L < 1 || L > OR_MAXL) return -1;
+  if (method == 1 && L != 2) return -1;
+  const int ncomp = (L + 1) * (L + 1) * 4;
+  /* quadrature set-up: shared rule, sigma tabulated per component at nodes */
+  rule_t rule = {0, NULL, NULL};
+  double* sig = NULL;
+  if ((parts & 2) && method == 0) {
+    double rho_max = 0.0, zeta_min = INFINITY;
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (x[j] < xmin) xmin = x[j];
+      if (x[j] > xmax) xmax = x[j];
+      if (y[j] < ymin) ymin = y[j];
+      if (y[j] > ymax) ymax = y[j];
+      const int l = layer[j];
+      if (l <= L - 1 && z[j] - d[l] < zeta_min) zeta_min = z[j] - d[l];
+      if (l >= 1 && d[l - 1] - z[j] < zeta_min) zeta_min = d[l - 1] - z[j];
+    }
+    rho_max = hypot(xmax - xmin, ymax - ymin);
+    zeta_min *= 2.0; /* every exponent is a target part plus a source part */
+    if (make_rule(rho_max, zeta_min, min_thickness(L, d), &rule)) return -3;
+    sig = (double*)malloc(sizeof(double) * (size_t)ncomp * rule.nn);
+    if (!sig) return -3;
+    for (int i = 0; i < rule.nn; ++i)
+      for (int lt = 0; lt <= L; ++lt)
+        for (int ls = 0; ls <= L; ++ls) {
+          double s4[4];
+          oracle_sigma(L, d, eps, lt, ls, rule.k[i], s4);
+          for (int c = 0; c < 4; ++c)
+            sig[(size_t)((lt * (L + 1) + ls) * 4 + c) * rule.nn + i] = s4[c];
+        }
+  }
+  /* image-series coefficients per component */
+  double* icoef = NULL;
+  int* ishift = NULL;
+  int* icnt = NULL;
+  const int MAXT = 1200;
+  if ((parts & 2) && method == 1) {
+    icoef = (double*)malloc(sizeof(double) * ncomp * MAXT);
+    ishift = (int*)malloc(sizeof(int) * ncomp * MAXT);
+    icnt = (int*)calloc(ncomp, sizeof(int));
+    if (!icoef || !ishift || !icnt) return -3;
+    for (int lt = 0; lt <= L; ++lt)
+      for (int ls = 0; ls <= L; ++ls)
+        for (int a = 1; a <= 2; ++a)
+          for (int b = 1; b <= 2; ++b) {
+            const int c = (lt * (L + 1) + ls) * 4 + 2 * (a - 1) + (b - 1);
+            if (valid_side(L, lt, a) && valid_side(L, ls, b))
+              icnt[c] = oracle_image3_terms(eps, lt, ls, a, b, MAXT, icoef + c * MAXT,
+                                            ishift + c * MAXT);
+          }
+  }
+  const double D = (L == 2) ? d[0] - d[1] : 0.0;
+  double* jbuf_all = NULL;
+  int nthr = oracle_num_threads();
+  if ((parts & 2) && method == 0) {
+    jbuf_all = (double*)malloc(sizeof(double) * (size_t)rule.nn * nthr);
+    if (!jbuf_all) return -3;
+  }
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t ti = 0; ti < nt; ++ti) {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    const int64_t i = targets[ti];
+    if (i < 0 || i >= n) { err = -4; continue; }
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const int li = layer[i];
+    double fs = 0.0, fc = 0.0; /* free part, Neumaier */
+    double rs = 0.0, rc = 0.0; /* reaction part, Neumaier */
+    for (int64_t j = 0; j < n; ++j) {
+      const double dx = xi - x[j], dy = yi - y[j];
+      const int lj = layer[j];
+      if ((parts & 1) && lj == li && j != i) {
+        const double dz = zi - z[j];
+        const double f = q[j] / (4.0 * OR_PI * sqrt(dx * dx + dy * dy + dz * dz));
+        const double t = fs + f;
+        if (fabs(fs) >= fabs(f)) fc += (fs - t) + f; else fc += (f - t) + fs;
+        fs = t;
+      }
+      if (parts & 2) {
+        const double rho = sqrt(dx * dx + dy * dy);
+        double v = 0.0;
+        if (method == 0) {
+          double* jb = jbuf_all + (size_t)tid * rule.nn;
+          for (int kk = 0; kk < rule.nn; ++kk) jb[kk] = rule.w[kk] * j0(rule.k[kk] * rho);
+          for (int a = 1; a <= 2; ++a)
+            for (int b = 1; b <= 2; ++b) {
+              if (!valid_side(L, li, a) || !valid_side(L, lj, b)) continue;
+              const double zeta = zeta_of(d, li, lj, a, b, zi, z[j]);
+              const double* sg =
+                  sig + (size_t)((li * (L + 1) + lj) * 4 + 2 * (a - 1) + (b - 1)) * rule.nn;
+              double acc = 0.0;
+              for (int kk = rule.nn - 1; kk >= 0; --kk)
+                acc += jb[kk] * exp(-rule.k[kk] * zeta) * sg[kk];
+              v += acc / (4.0 * OR_PI);
+            }
+        } else {
+          for (int a = 1; a <= 2; ++a)
+            for (int b = 1; b <= 2; ++b) {
+              if (!valid_side(L, li, a) || !valid_side(L, lj, b)) continue;
+              const double zeta = zeta_of(d, li, lj, a, b, zi, z[j]);
+              const int c = (li * (L + 1) + lj) * 4 + 2 * (a - 1) + (b - 1);
+              double acc = 0.0;
+              for (int t = icnt[c] - 1; t >= 0; --t) {
+                const double zz = zeta + ishift[c * MAXT + t] * D;
+                acc += icoef[c * MAXT + t] / sqrt(rho * rho + zz * zz);
+              }
+              v += acc / (4.0 * OR_PI);
+            }
+        }
+        const double f = q[j] * v;
+        const double t = rs + f;
+        if (fabs(rs) >= fabs(f)) rc += (rs - t) + f; else rc += (f - t) + rs;
+        rs = t;
+      }
+    }
+    phi_out[ti] = (fs + fc) + (rs + rc);
+  }
+  free(jbuf_all);
+  free(sig);
+  free_rule(&rule);
+  free(icoef);
+  free(ishift);
+  free(icnt);
+  return err;
+}

@@ -1,0 +1,371 @@
+"""Pins of the CPU oracle against facts fixed outside it: closed forms, the paper's
+worked values and printed tables, physical invariants and brute force.
+
+None of these compares the oracle with the GPU path.  A plausible slip in the oracle
+(a dropped term, a wrong sign or index, a transposed operand) fails at least one.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+D3 = [0.0, -1.0]
+E3 = [1.0, 5.0, 2.0]
+# the paper's own medium (Sec. 3.3 example and Sec. 4 tests)
+D3P = [0.0, -1.2]
+E3P = [21.2, 47.5, 62.8]
+VALID3 = [(lt, ls, a, b) for lt in range(3) for ls in range(3) for a in (1, 2) for b in (1, 2)
+          if (lt <= 1 if a == 1 else lt >= 1) and (ls <= 1 if b == 1 else ls >= 1)]
+
+
+def test_sixteen_three_layer_components(oracle_mod):
+    # Sec. 3.1 / Algorithm 2: 4L^2 reaction components, 16 for three layers
+    assert len(VALID3) == 16
+
+
+# ---------------------------------------------------------------- densities
+@pytest.mark.parametrize("e0,e1", [(1.0, 5.0), (21.2, 47.5), (3.0, 1.5)])
+def test_two_layer_image_charge(oracle_mod, e0, e1):
+    """A single interface: textbook image-charge coefficients, independent of k."""
+    for k in (0.0, 0.2, 1.0, 9.0):
+        s00 = oracle_mod.sigma([0.3], [e0, e1], 0, 0, k)
+        s10 = oracle_mod.sigma([0.3], [e0, e1], 1, 0, k)
+        s11 = oracle_mod.sigma([0.3], [e0, e1], 1, 1, k)
+        s01 = oracle_mod.sigma([0.3], [e0, e1], 0, 1, k)
+        assert s00[0] == pytest.approx((e0 - e1) / (e0 + e1), abs=1e-15)   # reflection above
+        assert s10[2] == pytest.approx(2 * e0 / (e0 + e1), abs=1e-15)      # transmission down
+        assert s11[3] == pytest.approx((e1 - e0) / (e0 + e1), abs=1e-15)   # reflection below
+        assert s01[1] == pytest.approx(2 * e1 / (e0 + e1), abs=1e-15)      # transmission up
+        # components that do not exist for a half-space are zero
+        assert s00[1] == s00[2] == s00[3] == 0.0
+
+
+@pytest.mark.parametrize("d,eps", [(D3, E3), (D3P, E3P), ([0.4, -0.35], [7.0, 1.2, 3.3])])
+def test_direct_solve_matches_three_layer_closed_forms(oracle_mod, d, eps):
+    """App. A explicit densities (with the kappa sign and sigma^{22}_{22} readings) equal
+    the direct interface solve for all 16 components."""
+    for k in (0.0, 0.05, 0.3, 1.0, 2.5, 7.0, 30.0):
+        for lt in range(3):
+            for ls in range(3):
+                a = oracle_mod.sigma(d, eps, lt, ls, k)
+                b = oracle_mod.sigma3(d, eps, lt, ls, k)
+                np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * max(1.0, np.abs(b).max()))
+
+
+def test_printed_kappa_and_sigma22_disagree_with_solve(oracle_mod):
+    """Documents the two readings: the formulas exactly as printed do not solve the
+    interface conditions (kappa with (e2-e1) in its x^2 term; sigma^{22}_{22} numerators)."""
+    e0, e1, e2 = E3P
+    D = D3P[0] - D3P[1]
+    k = 0.8
+    x2 = math.exp(-2 * D * k)
+    kap_printed = 0.5 * ((e0 + e1) * (e1 + e2) + (e0 - e1) * (e2 - e1) * x2)
+    s21_11_printed = (e1 - e2) * (e1 + e0) / (2 * kap_printed)
+    solved = oracle_mod.sigma(D3P, E3P, 1, 1, k)[0]
+    assert abs(s21_11_printed - solved) > 1e-4 * abs(solved)
+    s22_printed = ((e1 - e0) * (e1 + e2) + (e0 + e1) * (e2 - e1) * x2) / (2 * kap_printed)
+    assert abs(s22_printed - oracle_mod.sigma(D3P, E3P, 2, 2, k)[3]) > 1e-3
+
+
+def test_density_large_k_limits(oracle_mod):
+    """As k -> inf each density tends to the nearest single-interface coefficient
+    (eq. densityasymptotic with zeta_inf = 0 for direct reflections/transmissions)."""
+    e0, e1, e2 = E3
+    k = 60.0
+    s = oracle_mod.sigma(D3, E3, 0, 0, k)
+    assert s[0] == pytest.approx((e0 - e1) / (e0 + e1), abs=1e-14)
+    s = oracle_mod.sigma(D3, E3, 1, 1, k)
+    assert s[0] == pytest.approx((e1 - e2) / (e1 + e2), abs=1e-14)   # 11: off d_1
+    assert s[3] == pytest.approx((e1 - e0) / (e1 + e0), abs=1e-14)   # 22: off d_0
+    assert abs(s[1]) < 1e-20 and abs(s[2]) < 1e-20                    # cross terms decay
+    s = oracle_mod.sigma(D3, E3, 1, 0, k)
+    assert s[2] == pytest.approx(2 * e0 / (e0 + e1), abs=1e-14)
+
+
+def test_homogeneous_medium_densities(oracle_mod):
+    """All permittivities equal: no reflection, unit transmission (free space)."""
+    d = [0.0, -0.6, -1.4]
+    eps = [3.0, 3.0, 3.0, 3.0]
+    for k in (0.0, 0.7, 3.0):
+        for lt in range(4):
+            for ls in range(4):
+                s = oracle_mod.sigma(d, eps, lt, ls, k)
+                for a in (1, 2):
+                    for b in (1, 2):
+                        v = s[2 * (a - 1) + (b - 1)]
+                        if not (oracle_mod.valid(3, lt, a) and oracle_mod.valid(3, ls, b)):
+                            assert v == 0.0
+                            continue
+                        # the only non-zero density is the free wave passing unchanged
+                        # through the interfaces between the two layers: upward (b = 2)
+                        # into an upper target layer (a = 1), downward (b = 1) into a
+                        # lower one (a = 2); its amplitude is the decay across the gap.
+                        direct = (lt < ls and a == 1 and b == 2) or (lt > ls and a == 2 and b == 1)
+                        if lt < ls:
+                            expect = math.exp(-k * (d[lt] - d[ls - 1]))
+                        else:
+                            expect = math.exp(-k * (d[ls] - d[lt - 1])) if lt > ls else 0.0
+                        if direct:
+                            assert v == pytest.approx(expect, abs=1e-14)
+                        else:
+                            assert abs(v) < 1e-14
+
+
+# ---------------------------------------------------------------- kernels
+@pytest.mark.parametrize("rho,zeta", [(0.0, 0.2), (0.3, 0.2), (1.4, 0.2), (0.05, 2.0), (3.0, 0.5)])
+def test_quadrature_sommerfeld_identity(oracle_mod, rho, zeta):
+    """sigma == 1: int J0(k rho) e^{-k zeta} dk = 1/sqrt(rho^2 + zeta^2) (eq. freegreenintegral)."""
+    v = oracle_mod.reaction_quad([], [], 0, 0, 1, 1, rho, zeta)
+    assert v == pytest.approx(1.0 / (4 * math.pi * math.hypot(rho, zeta)), rel=1e-13)
+
+
+@pytest.mark.parametrize("d,eps", [(D3, E3), (D3P, E3P)])
+def test_quadrature_equals_image_series(oracle_mod, d, eps):
+    """Two independent routes to the three-layer reaction kernel: direct-solve density
+    under quadrature, and the closed-form density's image series."""
+    rng = np.random.default_rng(7)
+    for (lt, ls, a, b) in VALID3:
+        for _ in range(3):
+            rho = rng.uniform(0.0, 1.4)
+            zeta = rng.uniform(0.2, 2.2)
+            q = oracle_mod.reaction_quad(d, eps, lt, ls, a, b, rho, zeta)
+            s = oracle_mod.reaction_image3(d, eps, lt, ls, a, b, rho, zeta)
+            assert q == pytest.approx(s, rel=1e-12, abs=1e-15)
+
+
+def test_two_layer_potential_is_image_charge_sum(oracle_mod):
+    """Half-space: Phi = Coulomb in own layer + mirror image (coefficient (e_i-e_j)/(e_i+e_j))
+    + transmitted Coulomb from the other layer (coefficient 2 e_src/(e0+e1))."""
+    rng = np.random.default_rng(3)
+    n = 60
+    d0 = 0.25
+    e0, e1 = 2.0, 7.0
+    layer = (rng.uniform(size=n) < 0.5).astype(np.int32)
+    x = rng.uniform(-0.5, 0.5, n)
+    y = rng.uniform(-0.5, 0.5, n)
+    z = np.where(layer == 0, d0 + rng.uniform(0.1, 1.0, n), d0 - rng.uniform(0.1, 1.0, n))
+    q = rng.uniform(-1, 1, n)
+    phi = oracle_mod.potential([d0], [e0, e1], x, y, z, layer, q, method="quad")
+    eps = [e0, e1]
+    ref = np.zeros(n)
+    for i in range(n):
+        for j in range(n):
+            li, lj = layer[i], layer[j]
+            if li == lj:
+                if j != i:
+                    ref[i] += q[j] / (4 * math.pi * math.dist((x[i], y[i], z[i]), (x[j], y[j], z[j])))
+                R = (eps[li] - eps[1 - li]) / (e0 + e1)
+                zim = 2 * d0 - z[j]
+                ref[i] += R * q[j] / (4 * math.pi * math.dist((x[i], y[i], z[i]), (x[j], y[j], zim)))
+            else:
+                T = 2 * eps[lj] / (e0 + e1)
+                ref[i] += T * q[j] / (4 * math.pi * math.dist((x[i], y[i], z[i]), (x[j], y[j], z[j])))
+    np.testing.assert_allclose(phi, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_homogeneous_medium_potential_is_coulomb(oracle_mod):
+    """All permittivities equal: free + reaction = Coulomb sum over all charges of
+    all layers (the reaction part carries every cross-layer interaction)."""
+    rng = np.random.default_rng(11)
+    d = [0.0, -0.6, -1.4]
+    eps = [2.5] * 4
+    n = 40
+    layer = rng.integers(0, 4, n).astype(np.int32)
+    zr = {0: (0.1, 1.1), 1: (-0.5, -0.1), 2: (-1.3, -0.7), 3: (-2.5, -1.5)}
+    z = np.array([rng.uniform(*zr[l]) for l in layer])
+    x = rng.uniform(-0.5, 0.5, n)
+    y = rng.uniform(-0.5, 0.5, n)
+    q = rng.uniform(-1, 1, n)
+    phi = oracle_mod.potential(d, eps, x, y, z, layer, q, method="quad")
+    P = np.stack([x, y, z], 1)
+    R = np.linalg.norm(P[:, None] - P[None], axis=2)
+    np.fill_diagonal(R, np.inf)
+    ref = (q[None, :] / (4 * math.pi * R)).sum(1)
+    np.testing.assert_allclose(phi, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_reciprocity_four_layers(oracle_mod):
+    """u_{l l'}(r, r')/eps_{l'} = u_{l' l}(r', r)/eps_l, so q2.Phi(q1/eps) = q1.Phi(q2/eps)."""
+    rng = np.random.default_rng(5)
+    d = [0.0, -0.6, -1.4]
+    eps = [1.0, 3.9, 11.7, 2.5]
+    n = 36
+    layer = np.repeat(np.arange(4), n // 4).astype(np.int32)
+    zr = {0: (0.1, 1.1), 1: (-0.5, -0.1), 2: (-1.3, -0.7), 3: (-2.5, -1.5)}
+    z = np.array([rng.uniform(*zr[l]) for l in layer])
+    x = rng.uniform(-0.5, 0.5, n)
+    y = rng.uniform(-0.5, 0.5, n)
+    q1 = rng.uniform(-1, 1, n)
+    q2 = rng.uniform(-1, 1, n)
+    de = np.asarray(eps)[layer]
+    p1 = oracle_mod.potential(d, eps, x, y, z, layer, q1 / de, method="quad")
+    p2 = oracle_mod.potential(d, eps, x, y, z, layer, q2 / de, method="quad")
+    assert np.dot(q2, p1) == pytest.approx(np.dot(q1, p2), rel=1e-12)
+    # and the raw (unweighted) operator is NOT symmetric across layers
+    r1 = oracle_mod.potential(d, eps, x, y, z, layer, q1, method="quad")
+    r2 = oracle_mod.potential(d, eps, x, y, z, layer, q2, method="quad")
+    assert abs(np.dot(q2, r1) - np.dot(q1, r2)) > 1e-6 * abs(np.dot(q2, r1))
+
+
+def test_potential_methods_agree_three_layers(oracle_mod):
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(0, n=300)
+    t = np.arange(0, 300, 7)
+    a = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                             targets=t, method="image3")
+    b = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                             targets=t, method="quad")
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14 * np.abs(a).max())
+    # free + reaction decomposition (eq. totalinteraction)
+    f = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                             targets=t, parts=1)
+    r = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                             targets=t, parts=2)
+    np.testing.assert_allclose(f + r, a, rtol=1e-14, atol=1e-14)
+
+
+# ---------------------------------------------------------------- polarization sources
+def test_paper_polarization_example(oracle_mod):
+    """Sec. 3.3 worked example: r' = (0.625, 0.5, -0.1) in the middle layer of
+    d = (0, -1.2) gives r'_11 = (0.625, 0.5, -2.3), r'_22 = (0.625, 0.5, 0.1), and
+    |r'_ab - r_c^ab| ~ 0.1436 for centers (0.6, 0.6, -2.4) and (0.6, 0.6, 0.2)."""
+    z11 = oracle_mod.polarization_z(D3P, 1, 1, 1, 1, -0.1)
+    z22 = oracle_mod.polarization_z(D3P, 1, 1, 2, 2, -0.1)
+    assert z11 == pytest.approx(-2.3, abs=1e-14)
+    assert z22 == pytest.approx(0.1, abs=1e-14)
+    r1 = math.dist((0.625, 0.5, z11), (0.6, 0.6, -2.4))
+    r2 = math.dist((0.625, 0.5, z22), (0.6, 0.6, 0.2))
+    assert round(r1, 4) == 0.1436 and round(r2, 4) == 0.1436
+
+
+def test_polarization_distance_is_exponent(oracle_mod):
+    """eq. generalcomponentsimag: |z - z'_ab| equals the exponent zeta^{ab} of eq. zexponential."""
+    rng = np.random.default_rng(2)
+    d = [0.0, -0.6, -1.4]
+    zr = {0: (0.1, 1.1), 1: (-0.5, -0.1), 2: (-1.3, -0.7), 3: (-2.5, -1.5)}
+    for lt in range(4):
+        for ls in range(4):
+            for a in (1, 2):
+                for b in (1, 2):
+                    if not (oracle_mod.valid(3, lt, a) and oracle_mod.valid(3, ls, b)):
+                        continue
+                    z = rng.uniform(*zr[lt])
+                    zs = rng.uniform(*zr[ls])
+                    zp = oracle_mod.polarization_z(d, lt, ls, a, b, zs)
+                    assert abs(z - zp) == pytest.approx(oracle_mod.zeta_of(d, lt, ls, a, b, z, zs), abs=1e-14)
+                    # polarization sources sit across an interface from the targets
+                    if a == 1:
+                        assert zp < d[lt] < z
+                    else:
+                        assert z < d[lt - 1] < zp
+
+
+# ---------------------------------------------------------------- Sommerfeld integrals
+def _table31():
+    rows = []
+    with open(os.path.join(HERE, "golden", "table_3_1.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rho, n, m, pts, err = line.split()
+            rows.append((float(rho), int(n), int(m), int(pts), float(err)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _table31())
+def test_table_3_1_closed_form(oracle_mod, row):
+    """Table 3.1 cases: the sigma == 1 closed form is finite and the printed DE-SE
+    errors are small against it; the smallest-rho rows are re-derived by 30-digit
+    quadrature of the definition along the real axis."""
+    rho, n, m, _, err = row
+    z = 0.001
+    S = math.hypot(rho, z)
+    cf = oracle_mod.sommerfeld_sigma1(n, m, rho, z, S)
+    assert math.isfinite(cf)
+    assert abs(err) < 1e-9 * max(1.0, abs(cf))
+    if rho < z:
+        mp = oracle_mod.sommerfeld_mp([], [], 0, 0, 1, 1, n, m, rho, z, S, dps=30, path="real")
+        assert cf == pytest.approx(mp, rel=1e-13, abs=1e-13)
+
+
+def test_sigma1_closed_form_vs_scipy_quadrature(oracle_mod):
+    """r^n I_nm = sqrt(4 pi/(2n+1)) Phat_n^m(z/r)/r (sigma == 1) against adaptive
+    quadrature of int J_m(k rho) (kS)^n e^{-kz} dk / sqrt((n+m)!(n-m)!) where it
+    has no cancellation (rho <= z)."""
+    from scipy.integrate import quad
+    from scipy.special import jv
+    for (rho, z, S) in [(0.2, 0.3, 0.25), (0.05, 0.4, 0.1), (0.3, 0.3, 0.3)]:
+        for n in range(0, 11):
+            for m in range(0, n + 1):
+                nrm = math.sqrt(math.factorial(n + m) * math.factorial(n - m))
+                val, _ = quad(lambda k: jv(m, k * rho) * (k * S) ** n * math.exp(-k * z) / nrm,
+                              0, (n + 60) / z, limit=400, epsabs=1e-15, epsrel=1e-13)
+                cf = oracle_mod.sommerfeld_sigma1(n, m, rho, z, S)
+                assert cf == pytest.approx(val, rel=1e-10, abs=1e-13)
+
+
+def test_sommerfeld_image3_vs_high_precision(oracle_mod):
+    """Three-layer S^n I_nm: image series of the closed form against 20-digit quadrature
+    with the mpmath direct-solve density."""
+    cases = [(1, 1, 1, 1, 6, 0, 0.2, 0.25, 0.125), (0, 2, 1, 2, 7, 1, 0.3, 0.375, 0.125),
+             (2, 1, 2, 2, 4, 1, 0.0, 0.3, 0.1)]
+    for (lt, ls, a, b, n, m, rho, z, S) in cases:
+        im = oracle_mod.sommerfeld_image3(D3, E3, lt, ls, a, b, n, m, rho, z, S)
+        mp = oracle_mod.sommerfeld_mp(D3, E3, lt, ls, a, b, n, m, rho, z, S, dps=20, path="real")
+        assert im == pytest.approx(mp, rel=1e-11, abs=1e-14)
+
+
+def test_paper_recurrence_holds_on_closed_forms(oracle_mod):
+    """eq. recurrence: S^n I_{n,m+1} = 2m/a_{n+m} (S/rho) S^{n-1} I_{n-1,m}
+    - a_{n-m}/a_{n+m} S^n I_{n,m-1}, a_n = sqrt(n(n+1)), on closed-form values."""
+    rho, z, S = 0.5, 0.25, 0.125
+
+    def I(n, m):
+        return oracle_mod.sommerfeld_image3(D3, E3, 1, 1, 2, 2, n, m, rho, z, S)
+
+    def a(n):
+        return math.sqrt(n * (n + 1))
+    for n in range(2, 12):
+        for m in range(1, n):
+            lhs = I(n, m + 1)
+            rhs = 2 * m / a(n + m) * (S / rho) * I(n - 1, m) - a(n - m) / a(n + m) * I(n, m - 1)
+            assert lhs == pytest.approx(rhs, rel=1e-10, abs=1e-12 * abs(I(n, 0)))
+
+
+def test_zero_rho_kills_nonzero_orders(oracle_mod):
+    """rho = 0 gives I_nm = 0 for m > 0 (J_m(0) = 0), Sec. 3.4."""
+    for n in range(1, 8):
+        for m in range(1, n + 1):
+            assert abs(oracle_mod.sommerfeld_image3(D3, E3, 0, 0, 1, 1, n, m, 0.0, 0.3, 0.1)) < 1e-16
+
+
+# ---------------------------------------------------------------- tree keys
+def test_morton_keys_brute_force(oracle_mod):
+    """Bit interleave by explicit per-bit loops on a few points."""
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 1, 20)
+    y = rng.uniform(0, 1, 20)
+    h = rng.uniform(0, 1, 20)
+    scale = float(2 ** 21)
+    keys = oracle_mod.morton_keys(x, y, h, 0.0, 0.0, scale)
+    for i in range(20):
+        qx = min(int(math.floor(x[i] * scale)), 2 ** 21 - 1)
+        qy = min(int(math.floor(y[i] * scale)), 2 ** 21 - 1)
+        qh = min(int(math.floor(h[i] * scale)), 2 ** 21 - 1)
+        k = 0
+        for b in range(21):
+            k |= ((qx >> b) & 1) << (3 * b)
+            k |= ((qy >> b) & 1) << (3 * b + 1)
+            k |= ((qh >> b) & 1) << (3 * b + 2)
+        assert int(keys[i]) == k
+    # level-l box of a key is its top 3l bits
+    assert int(keys.max()) < 2 ** 63
+
+
+def test_morton_sort_is_stable(oracle_mod):
+    keys = np.array([5, 3, 5, 1, 3, 5], dtype=np.uint64)
+    sk, perm = oracle_mod.morton_sort(keys)
+    assert list(sk) == [1, 3, 3, 5, 5, 5]
+    assert list(perm) == [3, 1, 4, 0, 2, 5]
