@@ -1,0 +1,209 @@
+/*
+ * fmmlm.h -- C ABI of the MI355X (gfx950) fast multipole method for the 3-D
+ * Laplace equation in layered media (Wang, Zhang & Cai, arXiv:1908.10863).
+ *
+ * Problem (Sec. 3.1): a stack of L interfaces z = d_0 > d_1 > ... > d_{L-1}
+ * separates L+1 layers; layer l is d_l < z < d_{l-1} (layer 0 on top, layer L
+ * at the bottom) with permittivity eps_l.  Charges Q_j sit at r_j inside layer
+ * layer_id[j].  fmm_layered_eval returns, for every charge i in layer l,
+ *
+ *   Phi_i = sum_{j != i, layer j = l} Q_j / (4 pi |r_i - r_j|)           (free)
+ *         + sum_{all j, incl. j = i} Q_j u^r_{l, layer j}(r_i, r_j)     (reaction)
+ *
+ * (eqs. potential1 / totalinteraction), where the reaction Green's function is
+ * the sum of the four reaction components of eq. reactioncomponent, each a
+ * Sommerfeld integral of eq. generalcomponents with the densities of App. A
+ * (interface conditions: u and eps du/dz continuous).  The 1/(4 pi) factor is
+ * included in both parts.
+ *
+ * Conventions shared by every call:
+ *  - All functions return FMMLM_OK (0) or a negative error code; nothing is
+ *    thrown across the ABI.  fmm_layered_strerror turns a code into text; the
+ *    last HIP error message is kept per thread and appended.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory of the current device (e.g. torch tensors' data_ptr()).
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the default stream).
+ *    Plan-time work is synchronised before fmm_layered_plan returns;
+ *    fmm_layered_eval is asynchronous on hip_stream.
+ */
+#ifndef FMMLM_H
+#define FMMLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define FMMLM_OK 0
+#define FMMLM_EINVAL (-1)        /* null pointer, n < 1, nrhs out of range, p out of range, bad option */
+#define FMMLM_EINTERFACES (-2)   /* interfaces not strictly decreasing or not finite */
+#define FMMLM_EEPS (-3)          /* a permittivity is <= 0 or not finite */
+#define FMMLM_ELAYER (-4)        /* layer_id out of range or a point outside its layer */
+#define FMMLM_EONINTERFACE (-5)  /* a point lies on an interface (Sommerfeld integrals diverge) */
+#define FMMLM_EDEVICE (-6)       /* a HIP call failed */
+#define FMMLM_ENOMEM (-7)        /* host or device allocation failed, or a list exceeds its limit */
+#define FMMLM_EUNSUPPORTED (-8)  /* option combination not built */
+
+/* ---- options --------------------------------------------------------------- */
+#define FMMLM_PMAX 16            /* largest truncation order p (n = 0..p) */
+#define FMMLM_MAX_INTERFACES 12  /* largest L */
+
+#define FMMLM_FP64 0             /* every kernel in FP64 */
+#define FMMLM_FP32_COMPENSATED 1 /* P2P and M2L in FP32 with compensated sums (see fmmlm_opts) */
+
+#define FMMLM_FREE 1u            /* parts bit: free-space component */
+#define FMMLM_REACTION 2u        /* parts bit: reaction components */
+
+typedef struct fmmlm_plan_s* fmmlm_plan_t;
+
+typedef struct {
+  int32_t leaf_cap;        /* a box is split while it holds more points (default 64) */
+  int32_t precision;       /* FMMLM_FP64 (default) or FMMLM_FP32_COMPENSATED */
+  int32_t fp64_top_levels; /* FP32 form: tree levels 0..k-1 kept in FP64 (default 3) */
+  int32_t max_rhs;         /* largest nrhs accepted by eval (default 64) */
+  int32_t reserved[4];     /* must be 0 */
+} fmmlm_opts;
+
+/* Fills *opts with the defaults listed above. */
+void fmmlm_default_opts(fmmlm_opts* opts);
+
+/* ---- plan ------------------------------------------------------------------ */
+/*
+ * Builds an immutable plan for one geometry (Algorithm 2's set-up: trees,
+ * interaction lists, M2L operators with the Sommerfeld recurrence of
+ * eq. recurrence, near-field reaction kernels).
+ *
+ *  n_interfaces   L >= 1 (<= FMMLM_MAX_INTERFACES)
+ *  z_interfaces   [L] host or device, strictly decreasing, finite
+ *  eps            [L+1] host or device, > 0, top to bottom
+ *  n              number of charges, 1 <= n < 2^31
+ *  x, y, z        [n] host or device, SoA coordinates (FP64)
+ *  layer_id       [n] host or device, 0..L, with d_l < z < d_{l-1}
+ *  p              truncation order, 1..FMMLM_PMAX (expansions hold (p+1)^2 terms)
+ *  opts           NULL for defaults
+ *  hip_stream     stream for plan-time kernels
+ *  out            receives the plan; the caller owns it and frees it with
+ *                 fmm_layered_destroy.  Geometry is deep-copied: the caller may
+ *                 free its arrays after return.
+ *
+ * Errors: FMMLM_EINVAL, FMMLM_EINTERFACES, FMMLM_EEPS, FMMLM_ELAYER,
+ * FMMLM_EONINTERFACE (|z - d| below 1e-12 of the root box size),
+ * FMMLM_EDEVICE, FMMLM_ENOMEM.  On error *out is NULL.
+ */
+int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                     int64_t n, const double* x, const double* y, const double* z,
+                     const int32_t* layer_id, int32_t p, const fmmlm_opts* opts,
+                     void* hip_stream, fmmlm_plan_t* out);
+
+/* ---- evaluation ------------------------------------------------------------- */
+/*
+ * One matrix-vector product per charge vector: phi = G q (eq. totalinteraction).
+ *
+ *  nrhs           1..opts.max_rhs charge vectors
+ *  q              device, q[r * ldq + j] for r < nrhs, j < n (user order, FP64)
+ *  ldq            >= n
+ *  phi            device, phi[r * ldphi + i], overwritten (FP64)
+ *  ldphi          >= n; phi must not overlap q
+ *  parts          FMMLM_FREE | FMMLM_REACTION (both = total potential)
+ *  hip_stream     all work is enqueued here; nothing is synchronised
+ *
+ * The plan owns one workspace: evaluations of one plan must not overlap in
+ * time (enqueue them on one stream).  Errors: FMMLM_EINVAL, FMMLM_EDEVICE.
+ */
+int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t ldq,
+                     double* phi, int64_t ldphi, uint32_t parts, void* hip_stream);
+
+/* Frees the plan and its device memory (NULL is a no-op).  Synchronises the
+ * device first so that in-flight evaluations finish. */
+int fmm_layered_destroy(fmmlm_plan_t plan);
+
+/* Static text for an error code, followed by the calling thread's last HIP
+ * error message when there is one.  Never NULL. */
+const char* fmm_layered_strerror(int code);
+
+/* ---- introspection (tests, benchmarks) --------------------------------------- */
+typedef struct {
+  int64_t n_points;            /* n */
+  int64_t n_tree_points;       /* points over all interface-anchored trees */
+  int32_t n_trees;             /* 2L anchored trees */
+  int32_t p;
+  int32_t max_level;           /* deepest box level */
+  int32_t precision;
+  int64_t n_boxes;
+  int64_t n_leaves;
+  int64_t m2l_free_pairs;      /* source box -> target box free-space translations */
+  int64_t m2l_reaction_pairs;  /* reaction-component translations */
+  int64_t p2p_free_pairs;      /* particle pairs in the free-space near field */
+  int64_t p2p_reaction_pairs;  /* particle pairs in the reaction near field */
+  int64_t n_free_ops;          /* distinct free-space M2L operators */
+  int64_t n_reaction_ops;      /* distinct reaction M2L operators */
+  int64_t n_sommerfeld_tasks;  /* distinct (component, level, rho, z) integral sets */
+  double root_side;            /* common root box side W */
+  double x0, y0;               /* common xy origin */
+  double plan_seconds;         /* wall time of fmm_layered_plan */
+  int64_t device_bytes;        /* device memory held by the plan */
+} fmmlm_stats;
+
+int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
+
+/*
+ * Tree t (0 <= t < n_trees) of a plan.  Trees are ordered by layer, then side
+ * (1: heights above the layer's bottom interface d_l; 2: depths below its top
+ * interface d_{l-1}).  Outputs are host arrays; pass keys = perm = NULL to
+ * query *n only.  keys[i] is the 63-bit Morton key of the i-th point in tree
+ * order, perm[i] its user index.  Errors: FMMLM_EINVAL.
+ */
+int fmm_layered_plan_tree(fmmlm_plan_t plan, int32_t t, int32_t* layer, int32_t* side,
+                          int64_t* n, uint64_t* keys, int64_t* perm);
+
+/*
+ * The scaled Sommerfeld-type integrals S^N I^{ab}_{N,M}(rho, z) of
+ * eq. scaledsommerfeldint for 0 <= M <= N <= nmax, computed on the GPU the
+ * way plans compute them: 4 nmax + 1 initial values (M = 0, 1) by quadrature
+ * (real axis, or the K_M contour form of eq. contourchange when rho exceeds
+ * z plus the density's decay length), the rest by eq. recurrence.
+ *
+ *  medium         n_interfaces, z_interfaces [L], eps [L+1] (host); n_interfaces = 0
+ *                 selects sigma == 1
+ *  lt, ls, a, b   target layer, source layer, component indices (1 or 2)
+ *  S              scale factor (box size)
+ *  npts, rho, z   host arrays [npts]: rho >= 0 (the recurrence needs rho = 0 or
+ *                 rho >= S * 2 nmax / a_{2 nmax}), z > 0
+ *  nmax           <= 2 * FMMLM_PMAX
+ *  out            host [npts][(nmax+1)(nmax+2)/2], entry N(N+1)/2 + M
+ */
+int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                           int32_t lt, int32_t ls, int32_t a, int32_t b, double S, int64_t npts,
+                           const double* rho, const double* z, int32_t nmax, double* out,
+                           void* hip_stream);
+
+/*
+ * Reaction densities sigma^{ab}_{lt,ls}(k) of App. A at complex k (Re k >= 0),
+ * computed on the GPU by the plan's own routine.  Host arrays [nk].
+ */
+int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                        int32_t lt, int32_t ls, int32_t a, int32_t b, int64_t nk,
+                        const double* k_re, const double* k_im, double* out_re, double* out_im,
+                        void* hip_stream);
+
+/*
+ * Live per-stage timing of evaluations (benchmarks).  profile_begin makes the
+ * next max_evals evaluations of the plan record a HIP event on their stream
+ * before the first stage and after every stage (FMMLM_NSTAGES stages, in the
+ * order gather, P2M, M2M, M2L, L2L, L2P, P2P free, P2P reaction, combine).
+ * profile_end synchronises the device, writes the summed milliseconds of each
+ * stage over the recorded evaluations to stage_ms[FMMLM_NSTAGES] (host), the
+ * number of recorded evaluations to *n_evals, and stops recording.
+ * Errors: FMMLM_EINVAL, FMMLM_EDEVICE, FMMLM_ENOMEM.
+ */
+#define FMMLM_NSTAGES 9
+int fmm_layered_profile_begin(fmmlm_plan_t plan, int32_t max_evals);
+int fmm_layered_profile_end(fmmlm_plan_t plan, double* stage_ms, int64_t* n_evals);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMLM_H */

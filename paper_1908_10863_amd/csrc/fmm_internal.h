@@ -1,0 +1,176 @@
+// Internal declarations of the layered-media FMM library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmlm.h"
+
+namespace fmmlm {
+
+constexpr int kMaxL = FMMLM_MAX_INTERFACES;
+constexpr int kPMax = FMMLM_PMAX;
+constexpr int kMaxLevel = 20;  // 21-bit quantisation per axis
+
+// ---- small complex type (device and host) ------------------------------------
+struct cplx {
+  double re, im;
+};
+__host__ __device__ inline cplx cmk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ inline cplx operator+(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplx operator-(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplx operator*(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplx operator*(double s, cplx a) { return cplx{s * a.re, s * a.im}; }
+__host__ __device__ inline cplx cconj(cplx a) { return cplx{a.re, -a.im}; }
+__host__ __device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, den = b.re + b.im * r;
+    return cplx{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  }
+  const double r = b.re / b.im, den = b.re * r + b.im;
+  return cplx{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+__device__ inline cplx cexp_dev(cplx a) {
+  const double e = exp(a.re);
+  double s, c;
+  sincos(a.im, &s, &c);
+  return cplx{e * c, e * s};
+}
+
+// ---- layered medium (passed by value to kernels) ------------------------------
+struct Medium {
+  int L;                      // interfaces; 0 means sigma == 1 (test medium)
+  double d[kMaxL];            // interface heights, decreasing
+  double eps[kMaxL + 1];      // permittivities, top to bottom
+};
+
+// coefficient index of (n, m), 0 <= m <= n
+__host__ __device__ inline int cidx(int n, int m) { return n * (n + 1) / 2 + m; }
+__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
+
+// ---- host-side plan ----------------------------------------------------------
+struct TreeInfo {
+  int layer = 0, side = 0;       // side 1: h = z - d_l ; side 2: h = d_{l-1} - z
+  int64_t n = 0, pt_off = 0;     // points in global tree order [pt_off, pt_off + n)
+  std::vector<uint64_t> keys;    // sorted Morton keys (host copy, introspection)
+  std::vector<int64_t> perm;     // user index of each tree point (host copy)
+};
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace fmmlm
+
+struct fmmlm_plan_s {
+  int L = 0;
+  std::vector<double> d, eps;
+  fmmlm::Medium medium;
+  int64_t N = 0;
+  int p = 0, nc = 0, ng = 0;
+  fmmlm_opts opts;
+  double x0 = 0, y0 = 0, W = 0, scale = 0;
+  std::vector<fmmlm::TreeInfo> trees;
+  int64_t NP = 0;           // total tree points
+  int64_t NB = 0;           // total boxes
+  int maxlev = 0;
+  std::vector<int64_t> lev_off;  // global box index where level l starts, size maxlev + 2
+  int64_t nleaves = 0;
+  fmmlm_stats stats;
+
+  // device buffers (owned)
+  std::vector<fmmlm::DevBuf> bufs;
+  int64_t device_bytes = 0;
+
+  // points, tree order (global)
+  double *px = nullptr, *py = nullptr, *ph = nullptr;
+  int32_t* puser = nullptr;        // user index per tree point
+  int32_t* user_pos = nullptr;     // [N][2] tree positions of each user point (-1 if none)
+  // boxes (global, level-major)
+  double *bcx = nullptr, *bcy = nullptr, *bch = nullptr;
+  int32_t *blevel = nullptr, *bstart = nullptr, *bcount = nullptr, *bparent = nullptr;
+  int32_t *bchild0 = nullptr, *bnchild = nullptr;
+  int32_t* leaves = nullptr;       // leaf box ids
+  // M2L CSR over target boxes
+  int32_t *m2l_ptr = nullptr;      // [NB + 1] ; free entries first, then reaction
+  int32_t *m2l_nfree = nullptr;    // [NB] number of free entries per target box
+  int32_t *m2l_src = nullptr, *m2l_op = nullptr;  // op < 0 encodes mirrored source: ~op
+  double* G = nullptr;             // operators [nops][ng] complex (re, im interleaved)
+  int64_t nops = 0, n_free_ops = 0;
+  // P2P free, CSR over leaves
+  int32_t *p2p_ptr = nullptr;      // [nleaves + 1]
+  int32_t *p2p_src = nullptr;      // [2 * entries] (start, count)
+  // P2P reaction, CSR over leaves
+  int32_t *rp_ptr = nullptr;       // [nleaves + 1]
+  int32_t *rp_src = nullptr;       // [2 * entries] (start, count)
+  int64_t *rp_voff = nullptr;      // [entries] value offset
+  double *rp_val = nullptr;        // kernel values, row-major per entry (targets x sources)
+  // constants
+  double *coefA = nullptr;         // A_n^m for n <= 2p, m <= n : [cidx]
+  double *coefC2inv = nullptr;     // 1 / c_n^2, n <= p
+  // workspace
+  double *qt = nullptr, *phit = nullptr;
+  double *M = nullptr, *Lx = nullptr;  // [NB][nc] complex
+  double *sc_levels = nullptr;     // 1/S_l per level
+  // live stage timing
+  std::vector<hipEvent_t> prof_ev;  // [max_evals][FMMLM_NSTAGES + 1]
+  int prof_cap = 0, prof_used = 0;
+};
+
+namespace fmmlm {
+
+// ---- device entry points implemented in the .hip files ------------------------
+struct PlanBuildInput;
+
+// tree.hip
+int gpu_sort_tree(const double* dx, const double* dy, const double* dz, int64_t n, int side,
+                  double dref, double x0, double y0, double scale, uint64_t* keys_out,
+                  int64_t* perm_out, hipStream_t st, std::string* err);
+
+// sommerfeld.hip
+struct SommTask {
+  int comp;           // reaction component index into the component table
+  double S;           // box size at the level
+  double rho, z;      // horizontal and vertical centre distance
+};
+struct CompInfo {
+  int lt, ls, a, b;
+  double zinf;        // decay length of the density (shortest ray path)
+};
+int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,
+                          const std::vector<SommTask>& tasks, int nmax, double* d_out,
+                          hipStream_t st);
+int gpu_reaction_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
+                           const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
+                           int64_t npairs, const double* px, const double* py, const double* ph,
+                           double* d_val, hipStream_t st);
+int gpu_density(const Medium& md, const CompInfo& c, int64_t nk, const double* kre,
+                const double* kim, double* ore, double* oim, hipStream_t st);
+double zeta_inf(const Medium& md, int lt, int ls, int a, int b);
+
+// fmm.hip
+int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
+                  const std::vector<int>& reac_task, const std::vector<double>& reac_phi,
+                  const std::vector<double>& reac_S, const double* d_tables, hipStream_t st);
+int gpu_eval_one(fmmlm_plan_s* P, const double* q, double* phi, uint32_t parts, hipStream_t st,
+                 hipEvent_t* ev);
+
+void set_last_error(const std::string& s);
+
+}  // namespace fmmlm
+
+#define FMM_HIP_TRY(expr)                                                      \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess) {                                                    \
+      fmmlm::set_last_error(std::string(#expr) + ": " + hipGetErrorString(_e)); \
+      return FMMLM_EDEVICE;                                                    \
+    }                                                                          \
+  } while (0)

@@ -1,0 +1,436 @@
+// Reaction densities and Sommerfeld-type integrals on the GPU (plan time).
+//
+// * Densities sigma^{ab}_{l l'}(k) of App. A at complex k: the interface
+//   conditions (u and eps du/dz continuous) are resolved by the stable
+//   generalized-reflection recursion (downward and upward reflection
+//   coefficients seen through every layer stack, then transmission from the
+//   source layer to the target layer), valid for Re k >= 0.
+// * Initial values S^n I_{n,0} (n <= nmax) and S^n I_{n,1} (1 <= n <= nmax) of
+//   eq. scaledsommerfeldint: composite Gauss-Legendre quadrature with panels
+//   graded geometrically towards 0, along the real axis when rho <= z + zinf,
+//   otherwise along the imaginary axis in the K_m form of eq. contourchange
+//   (Sec. 3.4), zinf being the density's decay length (eq. densityasymptotic).
+// * The remaining orders by the forward recurrence of eq. recurrence.
+// * Reaction near-field kernels (1/4pi) I_{00} for particle pairs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmmlm {
+namespace {
+
+constexpr int kGL = 16;
+__constant__ double c_glx[kGL];
+__constant__ double c_glw[kGL];
+
+// ---------------------------------------------------------------- densities
+struct Scatter {
+  double Rdn[kMaxL], Tdn[kMaxL], Rup[kMaxL], Tup[kMaxL];
+};
+
+__device__ void local_coeffs(const Medium& md, Scatter& sc) {
+  for (int i = 0; i < md.L; ++i) {
+    const double e0 = md.eps[i], e1 = md.eps[i + 1], s = e0 + e1;
+    sc.Rdn[i] = (e0 - e1) / s;  // downgoing wave in layer i reflected at d_i
+    sc.Tdn[i] = 2.0 * e0 / s;   // ... transmitted into layer i+1
+    sc.Rup[i] = (e1 - e0) / s;  // upgoing wave in layer i+1 reflected at d_i
+    sc.Tup[i] = 2.0 * e1 / s;   // ... transmitted into layer i
+  }
+}
+
+// sigma^{ab}_{lt,ls}(k); k complex with Re k >= 0.
+__device__ cplx density(const Medium& md, const Scatter& sc, int lt, int ls, int a, int b, cplx k) {
+  const int L = md.L;
+  if (L == 0) return cmk(1.0, 0.0);
+  // propagation factor across finite layer i (1 <= i <= L-1): e_i = exp(-k D_i)
+  cplx e[kMaxL + 1], e2[kMaxL + 1];
+  for (int i = 0; i <= L; ++i) {
+    if (i >= 1 && i <= L - 1) {
+      const double D = md.d[i - 1] - md.d[i];
+      e[i] = cexp_dev(cmk(-k.re * D, -k.im * D));
+    } else {
+      e[i] = cmk(0.0, 0.0);
+    }
+    e2[i] = e[i] * e[i];
+  }
+  // generalized reflection looking down from layer i at d_i, and looking up
+  // from layer i+1 at d_i
+  cplx Gdn[kMaxL], Gup[kMaxL];
+  Gdn[L - 1] = cmk(sc.Rdn[L - 1], 0.0);
+  for (int i = L - 2; i >= 0; --i) {
+    const cplx x = e2[i + 1] * Gdn[i + 1];
+    const cplx num = (sc.Tdn[i] * sc.Tup[i]) * x;
+    const cplx den = cmk(1.0, 0.0) - sc.Rup[i] * x;
+    Gdn[i] = cmk(sc.Rdn[i], 0.0) + cdiv(num, den);
+  }
+  Gup[0] = cmk(sc.Rup[0], 0.0);
+  for (int i = 1; i <= L - 1; ++i) {
+    const cplx x = e2[i] * Gup[i - 1];
+    const cplx num = (sc.Tup[i] * sc.Tdn[i]) * x;
+    const cplx den = cmk(1.0, 0.0) - sc.Rdn[i] * x;
+    Gup[i] = cmk(sc.Rup[i], 0.0) + cdiv(num, den);
+  }
+  // amplitudes in the source layer: u (upgoing at d_ls), w (downgoing at d_{ls-1})
+  const cplx zero = cmk(0.0, 0.0), one = cmk(1.0, 0.0);
+  const cplx Rd = (ls <= L - 1) ? Gdn[ls] : zero;
+  const cplx Ru = (ls >= 1) ? Gup[ls - 1] : zero;
+  const cplx es = e[ls];
+  const cplx den = one - Rd * Ru * e2[ls];
+  cplx u, w;
+  if (b == 1) {
+    u = cdiv(Rd, den);
+    w = Ru * es * u;
+  } else {
+    w = cdiv(Ru, den);
+    u = Rd * es * w;
+  }
+  if (lt == ls) return (a == 1) ? u : w;
+  if (lt < ls) {
+    // upgoing amplitude s1 at the bottom interface of each layer above the source
+    cplx inc = (b == 2 ? one : zero) + es * u;  // upgoing at d_{ls-1} inside the source layer
+    cplx s1 = zero;
+    for (int i = ls - 1; i >= lt; --i) {
+      const cplx g = (i >= 1) ? Gup[i - 1] : zero;
+      const cplx dd = one - sc.Rdn[i] * (e2[i] * g);
+      s1 = cdiv(sc.Tup[i] * inc, dd);
+      inc = e[i] * s1;
+    }
+    if (a == 1) return s1;
+    return (lt >= 1) ? Gup[lt - 1] * (e[lt] * s1) : zero;
+  }
+  // lt > ls: downgoing amplitude s2 at the top interface of each layer below
+  cplx inc = (b == 1 ? one : zero) + es * w;  // downgoing at d_ls inside the source layer
+  cplx s2 = zero;
+  for (int i = ls + 1; i <= lt; ++i) {
+    const cplx g = (i <= L - 1) ? Gdn[i] : zero;
+    const cplx dd = one - sc.Rup[i - 1] * (e2[i] * g);
+    s2 = cdiv(sc.Tdn[i - 1] * inc, dd);
+    inc = e[i] * s2;
+  }
+  if (a == 2) return s2;
+  return (lt <= L - 1) ? Gdn[lt] * (e[lt] * s2) : zero;
+}
+
+// ---------------------------------------------------------------- Bessel K_0, K_1
+// K_m(x) = int_0^inf exp(-x cosh t) cosh(m t) dt (DLMF 10.32.9), trapezoidal
+// rule with step 1/8: the integrand is analytic in |Im t| < pi/2 and decays
+// double-exponentially, so the rule is accurate to roughly exp(-pi^2 / h).
+__device__ void bessel_k01(double x, double* k0, double* k1) {
+  const double h = 0.125;
+  const double eh = exp(h);
+  double E = 1.0;  // exp(t)
+  double s0 = 0.5 * exp(-x), s1 = 0.5 * exp(-x);
+  for (int i = 1; i < 4000; ++i) {
+    E *= eh;
+    const double ch = 0.5 * (E + 1.0 / E);
+    const double f = exp(-x * ch);
+    s0 += f;
+    s1 += f * ch;
+    if (x * ch > 745.0) break;
+  }
+  *k0 = h * s0;
+  *k1 = h * s1;
+}
+
+// ---------------------------------------------------------------- quadrature
+struct Panels {
+  double h0, ratio, hmax, kmax;
+};
+
+// geometric grading from h0 (ratio 1.25) up to hmax, then uniform to kmax
+__device__ inline double next_h(double h, const Panels& pn) {
+  const double t = h * pn.ratio;
+  return t < pn.hmax ? t : pn.hmax;
+}
+
+__device__ double min_thickness(const Medium& md) {
+  double m = 0.0;
+  for (int i = 1; i < md.L; ++i) {
+    const double t = md.d[i - 1] - md.d[i];
+    if (m == 0.0 || t < m) m = t;
+  }
+  return m;
+}
+
+__device__ double max_thickness(const Medium& md) {
+  double m = 0.0;
+  for (int i = 1; i < md.L; ++i) {
+    const double t = md.d[i - 1] - md.d[i];
+    if (t > m) m = t;
+  }
+  return m;
+}
+
+// S^n I_{n,0} -> out0[n] (n <= nmax), S^n I_{n,1} -> out1[n] (1 <= n <= nmax).
+// out1 may be null (only m = 0 wanted).  1/sqrt((n+m)!(n-m)!) included.
+__device__ void initial_values(const Medium& md, const Scatter& sc, const CompInfo& c, double S,
+                               double rho, double z, int nmax, double* out0, double* out1) {
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double acc0[kMaxN], acc1[kMaxN];
+  for (int n = 0; n <= nmax; ++n) acc0[n] = acc1[n] = 0.0;
+  const double zeff = z + c.zinf;
+  const bool contour = (rho > zeff) && (md.L > 0 || rho > z);
+  const double dmin = min_thickness(md);
+  double small = 1.0;
+  if (zeff < small) small = zeff;
+  if (dmin > 0.0 && dmin < small) small = dmin;
+  if (contour && rho < small) small = rho;
+  Panels pn;
+  pn.ratio = 1.25;
+  pn.h0 = 1e-3 * small;
+  const bool want1 = (out1 != nullptr) && rho > 0.0;
+  if (!contour) {
+    // real axis: J_m(k rho) (kS)^n e^{-kz} sigma(k)
+    pn.kmax = (2.0 * nmax + 50.0) / zeff;
+    double hmax = 2.0 / zeff;
+    if (rho > 0.0 && 3.14159265358979 / rho < hmax) hmax = 3.14159265358979 / rho;
+    if (dmin > 0.0 && 2.5 * dmin < hmax) hmax = 2.5 * dmin;
+    pn.hmax = hmax;
+    double k0 = 0.0, h = pn.h0;
+    while (k0 < pn.kmax) {
+      for (int g = 0; g < kGL; ++g) {
+        const double k = k0 + 0.5 * h * (c_glx[g] + 1.0);
+        const double w = 0.5 * h * c_glw[g];
+        const double sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(k, 0.0)).re : 1.0;
+        const double base = w * exp(-k * z) * sg;
+        const double j0v = (rho > 0.0) ? j0(k * rho) : 1.0;
+        const double j1v = want1 ? j1(k * rho) : 0.0;
+        double pw = 1.0;  // (kS)^n
+        const double ks = k * S;
+        for (int n = 0; n <= nmax; ++n) {
+          acc0[n] += base * j0v * pw;
+          acc1[n] += base * j1v * pw;
+          pw *= ks;
+        }
+      }
+      k0 += h;
+      h = next_h(h, pn);
+    }
+  } else {
+    // imaginary axis: (2/pi) K_m(eta rho) (S eta)^n x {(-1)^{(n-m)/2} Re w, (-1)^{(n-m+1)/2} Im w},
+    // w = e^{-i eta z} sigma(i eta)
+    pn.kmax = (2.0 * nmax + 50.0) / rho;
+    double hmax = 2.0 / rho;
+    const double osc = z + c.zinf + 4.0 * max_thickness(md);
+    if (3.14159265358979 / osc < hmax) hmax = 3.14159265358979 / osc;
+    pn.hmax = hmax;
+    double k0 = 0.0, h = pn.h0;
+    while (k0 < pn.kmax) {
+      for (int g = 0; g < kGL; ++g) {
+        const double et = k0 + 0.5 * h * (c_glx[g] + 1.0);
+        const double wq = 0.5 * h * c_glw[g] * (2.0 / 3.14159265358979323846);
+        cplx sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(0.0, et)) : cmk(1.0, 0.0);
+        double sn, cs;
+        sincos(et * z, &sn, &cs);
+        const cplx wv = cmk(cs, -sn) * sg;
+        double kk0, kk1;
+        bessel_k01(et * rho, &kk0, &kk1);
+        double pw = 1.0;
+        const double es = et * S;
+        for (int n = 0; n <= nmax; ++n) {
+          // m = 0: n even -> (-1)^{n/2} Re w ; n odd -> (-1)^{(n+1)/2} Im w
+          const double f0 = (n & 1) ? (((n + 1) / 2) & 1 ? -wv.im : wv.im)
+                                    : ((n / 2) & 1 ? -wv.re : wv.re);
+          acc0[n] += wq * kk0 * pw * f0;
+          if (want1 && n >= 1) {
+            // m = 1: n - 1 even -> (-1)^{(n-1)/2} Re w ; odd -> (-1)^{n/2} Im w
+            const double f1 = ((n - 1) & 1) ? ((n / 2) & 1 ? -wv.im : wv.im)
+                                            : (((n - 1) / 2) & 1 ? -wv.re : wv.re);
+            acc1[n] += wq * kk1 * pw * f1;
+          }
+          pw *= es;
+        }
+      }
+      k0 += h;
+      h = next_h(h, pn);
+    }
+  }
+  // normalisation 1/sqrt((n+m)!(n-m)!)
+  double fn = 1.0;  // n!
+  for (int n = 0; n <= nmax; ++n) {
+    if (n > 0) fn *= n;
+    out0[n] = acc0[n] / fn;
+    if (out1 != nullptr) {
+      if (n >= 1 && rho > 0.0) {
+        // (n+1)! (n-1)! = n!^2 (n+1)/n
+        out1[n] = acc1[n] / (fn * sqrt((n + 1.0) / n));
+      } else {
+        out1[n] = 0.0;
+      }
+    }
+  }
+}
+
+// One thread per task: initial values, then eq. recurrence for M >= 2.
+__global__ void sommerfeld_table_kernel(Medium md, const CompInfo* __restrict__ comps,
+                                        const SommTask* __restrict__ tasks, int ntask, int nmax,
+                                        double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  Scatter sc;
+  local_coeffs(md, sc);
+  const SommTask tk = tasks[t];
+  const CompInfo c = comps[tk.comp];
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double i0[kMaxN], i1[kMaxN];
+  initial_values(md, sc, c, tk.S, tk.rho, tk.z, nmax, i0, i1);
+  double* o = out + (int64_t)t * ncoef(nmax);
+  for (int n = 0; n <= nmax; ++n) {
+    o[cidx(n, 0)] = i0[n];
+    if (n >= 1) o[cidx(n, 1)] = i1[n];
+  }
+  // S^n I_{n,m+1} = (2m / a_{n+m}) (S / rho) S^{n-1} I_{n-1,m} - (a_{n-m} / a_{n+m}) S^n I_{n,m-1}
+  for (int m = 1; m + 1 <= nmax; ++m) {
+    for (int n = m + 1; n <= nmax; ++n) {
+      double v = 0.0;
+      if (tk.rho > 0.0) {
+        const double anpm = sqrt((double)(n + m) * (n + m + 1));
+        const double anmm = sqrt((double)(n - m) * (n - m + 1));
+        v = (2.0 * m / anpm) * (tk.S / tk.rho) * o[cidx(n - 1, m)] - (anmm / anpm) * o[cidx(n, m - 1)];
+      }
+      o[cidx(n, m + 1)] = v;
+    }
+  }
+}
+
+__global__ void nearfield_kernel(Medium md, const CompInfo* __restrict__ comps,
+                                 const int32_t* __restrict__ tpt, const int32_t* __restrict__ spt,
+                                 const int32_t* __restrict__ cmp, int64_t npairs,
+                                 const double* __restrict__ px, const double* __restrict__ py,
+                                 const double* __restrict__ ph, double* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  Scatter sc;
+  local_coeffs(md, sc);
+  const int32_t a = tpt[i], b = spt[i];
+  const double dx = px[a] - px[b], dy = py[a] - py[b];
+  const double rho = sqrt(dx * dx + dy * dy);
+  const double zeta = ph[a] + ph[b];
+  double v0;
+  initial_values(md, sc, comps[cmp[i]], 1.0, rho, zeta, 0, &v0, nullptr);
+  val[i] = v0 * (1.0 / (4.0 * 3.14159265358979323846));
+}
+
+__global__ void density_kernel(Medium md, CompInfo c, int64_t nk, const double* __restrict__ kre,
+                               const double* __restrict__ kim, double* __restrict__ ore,
+                               double* __restrict__ oim) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nk) return;
+  Scatter sc;
+  local_coeffs(md, sc);
+  const cplx v = density(md, sc, c.lt, c.ls, c.a, c.b, cmk(kre[i], kim[i]));
+  ore[i] = v.re;
+  oim[i] = v.im;
+}
+
+// Gauss-Legendre nodes on [-1, 1] (Newton on the three-term recurrence), host side.
+void gl_nodes(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int j = 2; j <= n; ++j) {
+      const double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+int upload_gl(hipStream_t st) {
+  static bool done = false;
+  (void)st;
+  if (done) return FMMLM_OK;
+  double x[kGL], w[kGL];
+  gl_nodes(kGL, x, w);
+  FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(x)));
+  FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(w)));
+  done = true;
+  return FMMLM_OK;
+}
+
+}  // namespace
+
+// Shortest ray path from the source's exit interface to the target's entry
+// interface: the density decays like exp(-k zinf) (eq. densityasymptotic).
+double zeta_inf(const Medium& md, int lt, int ls, int a, int b) {
+  if (md.L == 0) return 0.0;
+  auto D = [&](int l) { return (l >= 1 && l <= md.L - 1) ? md.d[l - 1] - md.d[l] : 0.0; };
+  if (lt == ls) return (a == b) ? 0.0 : D(lt);
+  if (lt < ls) return (b == 1 ? D(ls) : 0.0) + (md.d[lt] - md.d[ls - 1]) + (a == 2 ? D(lt) : 0.0);
+  return (b == 2 ? D(ls) : 0.0) + (md.d[ls] - md.d[lt - 1]) + (a == 1 ? D(lt) : 0.0);
+}
+
+int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,
+                          const std::vector<SommTask>& tasks, int nmax, double* d_out,
+                          hipStream_t st) {
+  if (tasks.empty()) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  CompInfo* dc = nullptr;
+  SommTask* dt = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMalloc(&dt, tasks.size() * sizeof(SommTask)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemcpyAsync(dt, tasks.data(), tasks.size() * sizeof(SommTask), hipMemcpyHostToDevice, st));
+  const int nt = (int)tasks.size();
+  sommerfeld_table_kernel<<<(nt + 63) / 64, 64, 0, st>>>(md, dc, dt, nt, nmax, d_out);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipStreamSynchronize(st));
+  hipFree(dc);
+  hipFree(dt);
+  return FMMLM_OK;
+}
+
+int gpu_reaction_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
+                           const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
+                           int64_t npairs, const double* px, const double* py, const double* ph,
+                           double* d_val, hipStream_t st) {
+  if (npairs == 0) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  CompInfo* dc = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  nearfield_kernel<<<(unsigned)((npairs + 63) / 64), 64, 0, st>>>(md, dc, d_tpt, d_spt, d_comp, npairs,
+                                                                  px, py, ph, d_val);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipStreamSynchronize(st));
+  hipFree(dc);
+  return FMMLM_OK;
+}
+
+int gpu_density(const Medium& md, const CompInfo& c, int64_t nk, const double* kre,
+                const double* kim, double* ore, double* oim, hipStream_t st) {
+  double* buf = nullptr;
+  FMM_HIP_TRY(hipMalloc(&buf, 4 * nk * sizeof(double)));
+  FMM_HIP_TRY(hipMemcpyAsync(buf, kre, nk * 8, hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemcpyAsync(buf + nk, kim, nk * 8, hipMemcpyHostToDevice, st));
+  density_kernel<<<(unsigned)((nk + 63) / 64), 64, 0, st>>>(md, c, nk, buf, buf + nk, buf + 2 * nk,
+                                                            buf + 3 * nk);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipMemcpyAsync(ore, buf + 2 * nk, nk * 8, hipMemcpyDeviceToHost, st));
+  FMM_HIP_TRY(hipMemcpyAsync(oim, buf + 3 * nk, nk * 8, hipMemcpyDeviceToHost, st));
+  FMM_HIP_TRY(hipStreamSynchronize(st));
+  hipFree(buf);
+  return FMMLM_OK;
+}
+
+}  // namespace fmmlm

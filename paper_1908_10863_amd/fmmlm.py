@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libfmmlm.so (include/fmmlm.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream; the binding
+raises when the library is missing, and has no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmmlm.so")
+
+FMMLM_FP64 = 0
+FMMLM_FP32_COMPENSATED = 1
+FREE = 1
+REACTION = 2
+
+_ERRORS = {
+    -1: ValueError, -2: ValueError, -3: ValueError, -4: ValueError, -5: ValueError,
+    -6: RuntimeError, -7: MemoryError, -8: NotImplementedError,
+}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("fp64_top_levels", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_tree_points", ctypes.c_int64),
+                ("n_trees", ctypes.c_int32), ("p", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("n_boxes", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("m2l_free_pairs", ctypes.c_int64),
+                ("m2l_reaction_pairs", ctypes.c_int64), ("p2p_free_pairs", ctypes.c_int64),
+                ("p2p_reaction_pairs", ctypes.c_int64), ("n_free_ops", ctypes.c_int64),
+                ("n_reaction_ops", ctypes.c_int64), ("n_sommerfeld_tasks", ctypes.c_int64),
+                ("root_side", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
+           "fmm_layered_strerror", "fmm_layered_plan_stats", "fmm_layered_plan_tree",
+           "fmm_layered_sommerfeld", "fmm_layered_density", "fmm_layered_profile_begin",
+           "fmm_layered_profile_end"]
+STAGES = ["gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "p2p_reaction", "combine"]
+
+_lib = None
+
+
+def lib():
+    """Load libfmmlm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.fmmlm_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.fmmlm_default_opts.restype = None
+    L.fmm_layered_plan.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int64, vp, vp, vp, vp,
+                                   ctypes.c_int32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.fmm_layered_plan.restype = ctypes.c_int
+    L.fmm_layered_eval.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                   ctypes.c_uint32, vp]
+    L.fmm_layered_eval.restype = ctypes.c_int
+    L.fmm_layered_destroy.argtypes = [vp]
+    L.fmm_layered_destroy.restype = ctypes.c_int
+    L.fmm_layered_strerror.argtypes = [ctypes.c_int]
+    L.fmm_layered_strerror.restype = ctypes.c_char_p
+    L.fmm_layered_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.fmm_layered_plan_stats.restype = ctypes.c_int
+    L.fmm_layered_plan_tree.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int64), vp, vp]
+    L.fmm_layered_plan_tree.restype = ctypes.c_int
+    L.fmm_layered_sommerfeld.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp]
+    L.fmm_layered_sommerfeld.restype = ctypes.c_int
+    L.fmm_layered_density.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp, vp,
+                                      vp, vp]
+    L.fmm_layered_density.restype = ctypes.c_int
+    L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
+    L.fmm_layered_profile_begin.restype = ctypes.c_int
+    L.fmm_layered_profile_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.fmm_layered_profile_end.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != 0:
+        msg = lib().fmm_layered_strerror(rc).decode()
+        raise _ERRORS.get(rc, RuntimeError)(f"fmmlm error {rc}: {msg}")
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
+
+    def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
+                 fp64_top_levels=3, max_rhs=64, stream=None):
+        self.d = _host(d, np.float64)
+        self.eps = _host(eps, np.float64)
+        x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)
+        layer = _host(layer, np.int32)
+        self.n = len(x)
+        o = Opts()
+        lib().fmmlm_default_opts(ctypes.byref(o))
+        o.leaf_cap = leaf_cap
+        o.precision = precision
+        o.fp64_top_levels = fp64_top_levels
+        o.max_rhs = max_rhs
+        h = ctypes.c_void_p()
+        rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
+                                    _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),
+                                    _stream_handle(stream), ctypes.byref(h))
+        check(rc)
+        self._h = h
+        self.p = p
+
+    def eval(self, q, parts=FREE | REACTION, out=None, stream=None):
+        """q: CUDA float64 tensor [n] or [nrhs, n] (user order) -> phi of the same shape."""
+        import torch
+        if not (q.is_cuda and q.dtype == torch.float64):
+            raise ValueError("q must be a CUDA float64 tensor")
+        q2 = q.reshape(-1, q.shape[-1]).contiguous()
+        if q2.shape[1] != self.n:
+            raise ValueError("q has the wrong length")
+        if out is None:
+            out = torch.empty_like(q2)
+        rc = lib().fmm_layered_eval(self._h, q2.shape[0], ctypes.c_void_p(q2.data_ptr()), self.n,
+                                    ctypes.c_void_p(out.data_ptr()), self.n, parts,
+                                    _stream_handle(stream))
+        check(rc)
+        return out.reshape(q.shape)
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(lib().fmm_layered_plan_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def tree(self, t):
+        lay = ctypes.c_int32()
+        side = ctypes.c_int32()
+        n = ctypes.c_int64()
+        check(lib().fmm_layered_plan_tree(self._h, t, ctypes.byref(lay), ctypes.byref(side),
+                                          ctypes.byref(n), None, None))
+        keys = np.zeros(n.value, np.uint64)
+        perm = np.zeros(n.value, np.int64)
+        check(lib().fmm_layered_plan_tree(self._h, t, None, None, None, _ptr(keys), _ptr(perm)))
+        return lay.value, side.value, keys, perm
+
+    def profile_begin(self, max_evals):
+        check(lib().fmm_layered_profile_begin(self._h, max_evals))
+
+    def profile_end(self):
+        """Summed milliseconds per stage over the recorded evaluations, and their count."""
+        ms = np.zeros(len(STAGES))
+        n = ctypes.c_int64()
+        check(lib().fmm_layered_profile_end(self._h, _ptr(ms), ctypes.byref(n)))
+        return dict(zip(STAGES, ms)), n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fmm_layered_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sommerfeld(d, eps, lt, ls, a, b, S, rho, z, nmax, stream=None):
+    """S^N I_{N,M}(rho, z) for 0 <= M <= N <= nmax on the GPU; d=[] means sigma == 1."""
+    d = _host(d, np.float64)
+    eps = _host(eps, np.float64) if len(d) else np.ones(1)
+    rho = _host(np.atleast_1d(rho), np.float64)
+    z = _host(np.atleast_1d(z), np.float64)
+    nc = (nmax + 1) * (nmax + 2) // 2
+    out = np.zeros((len(rho), nc))
+    check(lib().fmm_layered_sommerfeld(len(d), _ptr(d), _ptr(eps), lt, ls, a, b, float(S), len(rho),
+                                       _ptr(rho), _ptr(z), nmax, _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def density(d, eps, lt, ls, a, b, k, stream=None):
+    """sigma^{ab}_{lt,ls}(k) on the GPU for complex k (array)."""
+    d = _host(d, np.float64)
+    eps = _host(eps, np.float64)
+    k = np.atleast_1d(np.asarray(k, np.complex128))
+    kr = _host(k.real, np.float64)
+    ki = _host(k.imag, np.float64)
+    orr = np.zeros(len(k))
+    oi = np.zeros(len(k))
+    check(lib().fmm_layered_density(len(d), _ptr(d), _ptr(eps), lt, ls, a, b, len(k), _ptr(kr),
+                                    _ptr(ki), _ptr(orr), _ptr(oi), _stream_handle(stream)))
+    return orr + 1j * oi

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances:
+* tree keys and permutations: bit-exact;
+* densities and Sommerfeld tables (FP64, plan time): 1e-12 relative to the largest
+  value of the same degree N;
+* the FP64 FMM: relative L2 error vs the direct-sum oracle, <= 1e-7 at p = 12 (the
+  stated target), and the spectral decay with p at smaller orders.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+D3 = [0.0, -1.0]
+E3 = [1.0, 5.0, 2.0]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1908_10863_amd import fmmlm
+    fmmlm.lib()
+    return fmmlm
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------- densities
+@pytest.mark.parametrize("d,eps", [(D3, E3), ([0.0, -0.6, -1.4], [1.0, 3.9, 11.7, 2.5]),
+                                   ([0.3], [2.0, 7.0]),
+                                   ([0.0, -0.5, -1.0, -1.8, -2.6], [3.0, 1.5, 8.0, 11.0, 2.2, 6.5])])
+def test_density_real_k(dev, F, oracle_mod, d, eps):
+    _say(f"density real k L={len(d)}")
+    L = len(d)
+    ks = np.array([0.0, 0.01, 0.3, 1.0, 2.7, 9.0, 40.0])
+    for lt in range(L + 1):
+        for ls in range(L + 1):
+            for a in (1, 2):
+                for b in (1, 2):
+                    if not (oracle_mod.valid(L, lt, a) and oracle_mod.valid(L, ls, b)):
+                        continue
+                    g = F.density(d, eps, lt, ls, a, b, ks)
+                    o = np.array([oracle_mod.sigma(d, eps, lt, ls, k)[2 * (a - 1) + (b - 1)] for k in ks])
+                    np.testing.assert_allclose(g.real, o, rtol=1e-13, atol=1e-14)
+                    assert np.all(np.abs(g.imag) < 1e-15)
+
+
+def test_density_imaginary_axis(dev, F, oracle_mod):
+    """sigma(i eta) on the contour of eq. contourchange vs the mpmath interface solve."""
+    _say("density imaginary axis")
+    d, eps = [0.0, -0.6, -1.4], [1.0, 3.9, 11.7, 2.5]
+    etas = [0.3, 2.0, 7.5]
+    for (lt, ls, a, b) in [(0, 0, 1, 1), (1, 2, 2, 1), (3, 1, 2, 2), (2, 2, 1, 2)]:
+        g = F.density(d, eps, lt, ls, a, b, 1j * np.array(etas))
+        for e, v in zip(etas, g):
+            ref = complex(oracle_mod.sigma_mp(d, eps, lt, ls, 1j * e, dps=25)[2 * (a - 1) + (b - 1)])
+            assert abs(v - ref) < 1e-13 * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------- Sommerfeld tables
+def _table31():
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_3_1.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rho, n, m, pts, err = line.split()
+            rows.append((float(rho), int(n), int(m), int(pts), float(err)))
+    return rows
+
+
+def test_sommerfeld_table_3_1(dev, F, oracle_mod):
+    """sigma == 1, z = 0.001, S = r (Table 3.1): the GPU quadrature (real axis for rho <= z,
+    K_m contour otherwise) against the closed form, to the accuracy the paper prints for
+    its DE-SE rule."""
+    _say("sommerfeld table 3.1")
+    for rho, n, m, _, err in _table31():
+        z = 0.001
+        S = math.hypot(rho, z)
+        # initial values only (M = 0, 1) are quadratures; take the table at nmax = n
+        tab = F.sommerfeld([], [], 0, 0, 1, 1, S, [rho], [z], n)[0]
+        got = tab[n * (n + 1) // 2 + m]
+        ref = oracle_mod.sommerfeld_sigma1(n, m, rho, z, S)
+        assert abs(got - ref) <= max(10 * abs(err), 1e-12 * max(1.0, abs(ref))), (rho, n, m, got, ref)
+
+
+@pytest.mark.parametrize("nmax", [16, 20, 24])
+def test_sommerfeld_three_layer_tables(dev, F, oracle_mod, nmax):
+    """Full S^N I_{N,M} tables at M2L geometries (rho in {0} U [S, sqrt(18) S], z in
+    {1, 2, 3} S) for all 16 components against the image-series closed form."""
+    _say(f"sommerfeld 3-layer nmax={nmax}")
+    S = 0.1375
+    geo = [(0.0, 1), (1.0, 1), (math.sqrt(2), 2), (math.sqrt(8), 1), (math.sqrt(18), 1), (3.0, 3)]
+    rho = np.array([g[0] * S for g in geo])
+    z = np.array([g[1] * S for g in geo])
+    comps = [(lt, ls, a, b) for lt in range(3) for ls in range(3) for a in (1, 2) for b in (1, 2)
+             if oracle_mod.valid(2, lt, a) and oracle_mod.valid(2, ls, b)]
+    for (lt, ls, a, b) in comps:
+        tab = F.sommerfeld(D3, E3, lt, ls, a, b, S, rho, z, nmax)
+        for g in range(len(geo)):
+            for N in range(nmax + 1):
+                ref = np.array([oracle_mod.sommerfeld_image3(D3, E3, lt, ls, a, b, N, M, rho[g], z[g], S)
+                                for M in range(N + 1)])
+                got = tab[g, N * (N + 1) // 2: N * (N + 1) // 2 + N + 1]
+                scale = max(np.abs(ref).max(), 1e-300)
+                assert np.abs(got - ref).max() <= 1e-11 * scale, (lt, ls, a, b, g, N)
+
+
+# ---------------------------------------------------------------- tree
+@pytest.mark.parametrize("cfg,n", [(0, None), (1, 20000)])
+def test_tree_keys_bit_exact(dev, F, oracle_mod, cfg, n):
+    from paper_1908_10863_amd import workloads as W
+    _say(f"tree keys cfg={cfg}")
+    w = W.config(cfg, n=n)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=4, leaf_cap=w["leaf_cap"])
+    st = plan.stats()
+    scale = np.ldexp(1.0, 21) / st["root_side"]
+    d = w["d"]
+    for t in range(st["n_trees"]):
+        layer, side, keys, perm = plan.tree(t)
+        members = np.nonzero(w["layer"] == layer)[0]
+        h = (w["z"][members] - d[layer]) if side == 1 else (d[layer - 1] - w["z"][members])
+        ok = oracle_mod.morton_keys(w["x"][members], w["y"][members], h, st["x0"], st["y0"], scale)
+        sk, sp = oracle_mod.morton_sort(ok)
+        assert np.array_equal(keys, sk)
+        assert np.array_equal(perm, members[sp])
+    plan.close()
+
+
+# ---------------------------------------------------------------- FMM end to end
+def _run(F, w, p, dev, parts=3, leaf_cap=None, q=None):
+    import torch
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p,
+                  leaf_cap=leaf_cap or w["leaf_cap"])
+    qq = torch.tensor(w["q"][0] if q is None else q, dtype=torch.float64, device=dev)
+    phi = plan.eval(qq, parts=parts).cpu().numpy()
+    st = plan.stats()
+    plan.close()
+    return phi, st
+
+
+def test_config1_p8_full_oracle(dev, F, oracle_mod):
+    """Workload 1 (N = 1200, p = 8, <= 40 per leaf) against the full N^2 direct sum,
+    free and reaction parts separately and together."""
+    from paper_1908_10863_amd import workloads as W
+    _say("config1 p=8")
+    w = W.config(0)
+    args = (w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    ref_f = oracle_mod.potential(*args, parts=1)
+    ref_r = oracle_mod.potential(*args, parts=2)
+    phi_f, st = _run(F, w, 8, dev, parts=1)
+    phi_r, _ = _run(F, w, 8, dev, parts=2)
+    phi, _ = _run(F, w, 8, dev, parts=3)
+    ef, er, et = relerr(phi_f, ref_f), relerr(phi_r, ref_r), relerr(phi, ref_f + ref_r)
+    _say(f"  free {ef:.3e} reaction {er:.3e} total {et:.3e} stats {st}")
+    assert ef < 2e-6 and er < 2e-6 and et < 2e-6
+    np.testing.assert_allclose(phi_f + phi_r, phi, rtol=0, atol=1e-12 * np.abs(phi).max())
+
+
+def test_config1_p12_meets_1e7(dev, F, oracle_mod):
+    from paper_1908_10863_amd import workloads as W
+    _say("config1 p=12")
+    w = W.config(0)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    phi, _ = _run(F, w, 12, dev)
+    e = relerr(phi, ref)
+    _say(f"  p=12 rel L2 {e:.3e}")
+    assert e <= 1e-7
+
+
+def test_spectral_convergence_in_p(dev, F, oracle_mod):
+    """Errors fall geometrically with p (Sec. 4, Fig. fmmconvergence (b) analogue)."""
+    from paper_1908_10863_amd import workloads as W
+    _say("convergence in p")
+    w = W.config(0)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    errs = []
+    for p in (2, 4, 6, 8, 10):
+        phi, _ = _run(F, w, p, dev)
+        errs.append(relerr(phi, ref))
+    _say(f"  errors {errs}")
+    for a, b in zip(errs, errs[1:]):
+        assert b < 0.5 * a
+    assert errs[-1] < 1e-6
+
+
+def test_four_layer_quadrature_oracle(dev, F, oracle_mod):
+    """A four-layer medium (workload 4's interfaces) at small N against the quadrature
+    oracle (no closed form used anywhere)."""
+    from paper_1908_10863_amd import workloads as W
+    _say("four layers")
+    w = W.config(3, n=600)
+    t = np.arange(0, 600, 5)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                               targets=t, method="quad")
+    phi, st = _run(F, w, 10, dev, leaf_cap=20)
+    e = relerr(phi[t], ref)
+    _say(f"  rel L2 {e:.3e} m2l_reaction {st['m2l_reaction_pairs']}")
+    assert e < 1e-7
+
+
+def test_two_layer_close_to_interface(dev, F, oracle_mod):
+    """Points close to a single interface exercise the reaction near field (P2P with
+    per-pair Sommerfeld kernels)."""
+    _say("two layers near interface")
+    rng = np.random.default_rng(9)
+    n = 800
+    lay = (rng.uniform(size=n) < 0.5).astype(np.int32)
+    x = rng.uniform(-0.5, 0.5, n)
+    y = rng.uniform(-0.5, 0.5, n)
+    z = np.where(lay == 0, rng.uniform(0.002, 0.3, n), -rng.uniform(0.002, 0.3, n))
+    w = dict(d=np.array([0.0]), eps=np.array([2.0, 9.0]), x=x, y=y, z=z, layer=lay,
+             q=rng.uniform(-1, 1, (1, n)), leaf_cap=16)
+    t = np.arange(0, n, 4)
+    ref = oracle_mod.potential(w["d"], w["eps"], x, y, z, lay, w["q"][0], targets=t, method="quad")
+    phi, st = _run(F, w, 10, dev)
+    _say(f"  reaction near pairs {st['p2p_reaction_pairs']}")
+    assert st["p2p_reaction_pairs"] > 0
+    assert relerr(phi[t], ref) < 1e-7
+
+
+def test_homogeneous_medium_is_coulomb(dev, F):
+    """All permittivities equal: the layered FMM reproduces the plain Coulomb sum over
+    all charges across layers."""
+    from paper_1908_10863_amd import workloads as W
+    _say("homogeneous")
+    w = W.config(0, n=900)
+    w["eps"] = np.array([3.0, 3.0, 3.0])
+    P = np.stack([w["x"], w["y"], w["z"]], 1)
+    R = np.linalg.norm(P[:, None] - P[None], axis=2)
+    np.fill_diagonal(R, np.inf)
+    ref = (w["q"][0][None, :] / (4 * math.pi * R)).sum(1)
+    phi, _ = _run(F, w, 10, dev)
+    assert relerr(phi, ref) < 1e-7
+
+
+def test_multiple_rhs_and_determinism(dev, F):
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say("multi rhs")
+    w = W.config(0, n=600)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=6, leaf_cap=30)
+    rng = np.random.default_rng(1)
+    Q = torch.tensor(rng.uniform(-1, 1, (3, 600)), dtype=torch.float64, device=dev)
+    both = plan.eval(Q).cpu().numpy()
+    for r in range(3):
+        one = plan.eval(Q[r].contiguous()).cpu().numpy()
+        assert np.array_equal(one, both[r])
+    again = plan.eval(Q).cpu().numpy()
+    assert np.array_equal(again, both)
+    # linearity
+    lin = plan.eval((2.0 * Q[0] - Q[1]).contiguous()).cpu().numpy()
+    np.testing.assert_allclose(lin, 2 * both[0] - both[1], rtol=0, atol=1e-12 * np.abs(lin).max())
+    plan.close()
+
+
+def test_tiny_and_ragged_inputs(dev, F, oracle_mod):
+    """One charge, two charges, an empty layer, and a leaf cap of 1."""
+    import torch
+    _say("tiny inputs")
+    cases = [
+        (np.array([0.1]), np.array([0.2]), np.array([0.5]), np.array([0]), 8),
+        (np.array([0.1, -0.2]), np.array([0.2, 0.0]), np.array([0.5, -0.4]), np.array([0, 1]), 1),
+        (np.array([0.1, -0.2, 0.3]), np.array([0.2, 0.0, -0.1]), np.array([0.5, 0.6, -1.5]),
+         np.array([0, 0, 2]), 1),
+    ]
+    for x, y, z, lay, cap in cases:
+        q = np.linspace(-1, 1, len(x)) + 0.3
+        plan = F.Plan(D3, E3, x, y, z, lay, p=8, leaf_cap=cap)
+        phi = plan.eval(torch.tensor(q, dtype=torch.float64, device=dev)).cpu().numpy()
+        ref = oracle_mod.potential(D3, E3, x, y, z, lay, q)
+        np.testing.assert_allclose(phi, ref, rtol=1e-10, atol=1e-13)
+        plan.close()
+
+
+@pytest.mark.parametrize("cfg,p,tol", [(1, 12, 1e-7), (2, 10, 1e-6)])
+def test_full_size_sampled(dev, F, oracle_mod, cfg, p, tol):
+    """Workloads 2 (N = 262144, clustered middle layer) and 3 (N = 1048576) at full size,
+    checked on 64 sampled targets against the direct sum over all N sources."""
+    from paper_1908_10863_amd import workloads as W
+    _say(f"full size cfg={cfg} p={p}")
+    w = W.config(cfg)
+    rng = np.random.default_rng(123)
+    t = np.sort(rng.choice(len(w["x"]), 64, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                               targets=t)
+    phi, st = _run(F, w, p, dev)
+    e = relerr(phi[t], ref)
+    _say(f"  rel L2 {e:.3e} plan {st['plan_seconds']:.2f}s boxes {st['n_boxes']}")
+    assert e <= tol
