@@ -63,7 +63,11 @@ typedef struct {
   int32_t precision;       /* FMMLM_FP64 (default) or FMMLM_FP32_COMPENSATED */
   int32_t fp64_top_levels; /* FP32 form: tree levels 0..k-1 kept in FP64 (default 3) */
   int32_t max_rhs;         /* largest nrhs accepted by eval (default 64) */
-  int32_t reserved[4];     /* must be 0 */
+  int32_t mac_d2;          /* multipole acceptance: two same-level boxes exchange expansions
+                              only if their centres are at least sqrt(mac_d2) box sizes apart
+                              (and not adjacent); 4 is the classic one-box separation.
+                              Range 4..12, default 6 */
+  int32_t reserved[3];     /* must be 0 */
 } fmmlm_opts;
 
 /* Fills *opts with the defaults listed above. */

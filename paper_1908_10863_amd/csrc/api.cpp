@@ -107,6 +107,7 @@ inline int compact1by2(uint64_t v) {
 
 struct Builder {
   fmmlm_plan_s* P;
+  int mac_d2 = 4;
   std::vector<HBox> boxes;                 // global, level-major
   std::vector<int> root;                   // per tree
   // M2L triples
@@ -169,10 +170,11 @@ struct Builder {
       for (int j = 0; j < cc.nchild; ++j) {
         const int c = cc.child0 + j;
         const int dx = boxes[b].ix - boxes[c].ix, dy = boxes[b].iy - boxes[c].iy, dz = boxes[b].ih - boxes[c].ih;
-        if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) {
+        const bool adjacent = std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1;
+        if (adjacent || dx * dx + dy * dy + dz * dz < mac_d2) {
           process_free(b, c);
         } else {
-          const int code = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+          const int code = (dx + 7) * 225 + (dy + 7) * 15 + (dz + 7);
           if (free_code_to_op[code] < 0) {
             free_code_to_op[code] = (int)(free_off.size() / 3);
             free_off.push_back(dx);
@@ -201,7 +203,8 @@ struct Builder {
         const int c = cc.child0 + j;
         const int dx = boxes[b].ix - boxes[c].ix, dy = boxes[b].iy - boxes[c].iy;
         const int dz = boxes[b].ih + boxes[c].ih + 1;  // target above, mirrored source below
-        if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && dz == 1) {
+        const bool adjacent = std::abs(dx) <= 1 && std::abs(dy) <= 1 && dz == 1;
+        if (adjacent || dx * dx + dy * dy + dz * dz < mac_d2) {
           process_reac(b, c, comp);
         } else {
           const int lvl = boxes[b].level;
@@ -400,7 +403,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     bx.ih = compact1by2(pf >> 2);
   }
   // ---- interaction lists
-  B.free_code_to_op.assign(343, -1);
+  B.free_code_to_op.assign(15 * 15 * 15, -1);
+  B.mac_d2 = P->opts.mac_d2;
   B.p2p_free.resize(P->NB);
   B.p2p_reac.resize(P->NB);
   for (int t = 0; t < nt; ++t) {
@@ -510,6 +514,18 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   }
   P->stats.p2p_free_pairs = B.free_pairs;
   P->stats.p2p_reaction_pairs = B.reac_pairs;
+  // ---- leaf of every tree point, free-space point ranges
+  std::vector<int32_t> pleaf(P->NP, -1);
+  for (int64_t li = 0; li < P->nleaves; ++li) {
+    const HBox& bx = B.boxes[leaves[li]];
+    P->max_leaf = std::max<int64_t>(P->max_leaf, bx.count);
+    for (int64_t g = bx.start; g < bx.start + bx.count; ++g) pleaf[g] = (int32_t)li;
+  }
+  for (int t = 0; t < nt; ++t) {
+    const TreeInfo& T = P->trees[t];
+    const bool free_tree = (T.layer <= L - 1) ? (T.side == 1) : (T.side == 2);
+    if (free_tree) P->free_ranges.push_back({T.pt_off, T.n});
+  }
   // ---- points in tree order
   std::vector<double> px(P->NP), py(P->NP), ph(P->NP);
   std::vector<int32_t> puser(P->NP), upos(2 * N, -1);
@@ -536,7 +552,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   // ---- uploads
   int rc;
 #define UP(field, vec) if ((rc = dev_upload(P, &P->field, vec, st))) return rc
-  UP(px, px); UP(py, py); UP(ph, ph); UP(puser, puser); UP(user_pos, upos);
+  UP(px, px); UP(py, py); UP(ph, ph); UP(puser, puser); UP(user_pos, upos); UP(pleaf, pleaf);
   UP(bcx, bcx); UP(bcy, bcy); UP(bch, bch); UP(blevel, blevel); UP(bstart, bstart); UP(bcount, bcount);
   UP(bparent, bparent); UP(bchild0, bchild0); UP(bnchild, bnchild); UP(leaves, leaves);
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
@@ -600,6 +616,7 @@ void fmmlm_default_opts(fmmlm_opts* o) {
   o->precision = FMMLM_FP64;
   o->fp64_top_levels = 3;
   o->max_rhs = 64;
+  o->mac_d2 = 6;
 }
 
 int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const double* eps, int64_t n,
@@ -616,8 +633,9 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   fmmlm_default_opts(&o);
   if (opts) o = *opts;
   if (o.leaf_cap < 1 || o.max_rhs < 1) return FMMLM_EINVAL;
+  if (o.mac_d2 < 4 || o.mac_d2 > 12) return FMMLM_EINVAL;
   if (o.precision != FMMLM_FP64 && o.precision != FMMLM_FP32_COMPENSATED) return FMMLM_EINVAL;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (o.reserved[i] != 0) return FMMLM_EINVAL;
   if (o.precision != FMMLM_FP64) return FMMLM_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);

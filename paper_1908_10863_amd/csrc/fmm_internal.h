@@ -98,6 +98,9 @@ struct fmmlm_plan_s {
   int32_t *blevel = nullptr, *bstart = nullptr, *bcount = nullptr, *bparent = nullptr;
   int32_t *bchild0 = nullptr, *bnchild = nullptr;
   int32_t* leaves = nullptr;       // leaf box ids
+  int32_t* pleaf = nullptr;        // leaf list index of every tree point
+  int64_t max_leaf = 0;            // largest leaf population
+  std::vector<std::pair<int64_t, int64_t>> free_ranges;  // (first point, count) of free-space trees
   // M2L CSR over target boxes
   int32_t *m2l_ptr = nullptr;      // [NB + 1] ; free entries first, then reaction
   int32_t *m2l_nfree = nullptr;    // [NB] number of free entries per target box

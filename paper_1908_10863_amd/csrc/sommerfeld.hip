@@ -23,6 +23,9 @@ namespace fmmlm {
 namespace {
 
 constexpr int kGL = 16;
+// The first panel [0, h0] is replaced by [0, h0 2^-Z] and [h0 2^-k, h0 2^-(k-1)],
+// k = Z..1, which integrates the logarithmic singularity of K_0 at 0 to full accuracy.
+constexpr int kZoom = 40;
 __constant__ double c_glx[kGL];
 __constant__ double c_glw[kGL];
 
@@ -190,10 +193,16 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
     if (dmin > 0.0 && 2.5 * dmin < hmax) hmax = 2.5 * dmin;
     pn.hmax = hmax;
     double k0 = 0.0, h = pn.h0;
+    int zoom = kZoom + 1;  // first panel [0, h0] split geometrically towards 0
     while (k0 < pn.kmax) {
+      double a0 = k0, hh = h;
+      if (zoom > 0) {
+        hh = (zoom > kZoom) ? ldexp(pn.h0, -kZoom) : ldexp(pn.h0, -zoom);
+        a0 = (zoom > kZoom) ? 0.0 : hh;
+      }
       for (int g = 0; g < kGL; ++g) {
-        const double k = k0 + 0.5 * h * (c_glx[g] + 1.0);
-        const double w = 0.5 * h * c_glw[g];
+        const double k = a0 + 0.5 * hh * (c_glx[g] + 1.0);
+        const double w = 0.5 * hh * c_glw[g];
         const double sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(k, 0.0)).re : 1.0;
         const double base = w * exp(-k * z) * sg;
         const double j0v = (rho > 0.0) ? j0(k * rho) : 1.0;
@@ -205,6 +214,10 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
           acc1[n] += base * j1v * pw;
           pw *= ks;
         }
+      }
+      if (zoom > 0) {
+        --zoom;
+        if (zoom > 0) continue;
       }
       k0 += h;
       h = next_h(h, pn);
@@ -218,10 +231,16 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
     if (3.14159265358979 / osc < hmax) hmax = 3.14159265358979 / osc;
     pn.hmax = hmax;
     double k0 = 0.0, h = pn.h0;
+    int zoom = kZoom + 1;
     while (k0 < pn.kmax) {
+      double a0 = k0, hh = h;
+      if (zoom > 0) {
+        hh = (zoom > kZoom) ? ldexp(pn.h0, -kZoom) : ldexp(pn.h0, -zoom);
+        a0 = (zoom > kZoom) ? 0.0 : hh;
+      }
       for (int g = 0; g < kGL; ++g) {
-        const double et = k0 + 0.5 * h * (c_glx[g] + 1.0);
-        const double wq = 0.5 * h * c_glw[g] * (2.0 / 3.14159265358979323846);
+        const double et = a0 + 0.5 * hh * (c_glx[g] + 1.0);
+        const double wq = 0.5 * hh * c_glw[g] * (2.0 / 3.14159265358979323846);
         cplx sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(0.0, et)) : cmk(1.0, 0.0);
         double sn, cs;
         sincos(et * z, &sn, &cs);
@@ -243,6 +262,10 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
           }
           pw *= es;
         }
+      }
+      if (zoom > 0) {
+        --zoom;
+        if (zoom > 0) continue;
       }
       k0 += h;
       h = next_h(h, pn);

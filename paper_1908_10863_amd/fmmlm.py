@@ -28,7 +28,7 @@ _ERRORS = {
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("fp64_top_levels", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("mac_d2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -121,7 +121,7 @@ class Plan:
     """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
 
     def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
-                 fp64_top_levels=3, max_rhs=64, stream=None):
+                 fp64_top_levels=3, max_rhs=64, mac_d2=None, stream=None):
         self.d = _host(d, np.float64)
         self.eps = _host(eps, np.float64)
         x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)
@@ -133,6 +133,8 @@ class Plan:
         o.precision = precision
         o.fp64_top_levels = fp64_top_levels
         o.max_rhs = max_rhs
+        if mac_d2 is not None:
+            o.mac_d2 = mac_d2
         h = ctypes.c_void_p()
         rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
                                     _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),

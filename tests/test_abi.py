@@ -41,7 +41,7 @@ def test_default_opts(L):
     from paper_1908_10863_amd import fmmlm
     o = fmmlm.Opts()
     L.fmmlm_default_opts(ctypes.byref(o))
-    assert (o.leaf_cap, o.precision, o.fp64_top_levels, o.max_rhs) == (64, 0, 3, 64)
+    assert (o.leaf_cap, o.precision, o.fp64_top_levels, o.max_rhs, o.mac_d2) == (64, 0, 3, 64, 6)
 
 
 def test_strerror_never_null(L):
@@ -99,6 +99,16 @@ def test_reserved_options_rejected(L):
     o.reserved[0] = 1
     rc, _ = _plan_rc(L, [0.0], [1.0, 2.0], [0.0], [0.0], [0.5], [0], 4, o)
     assert rc == -1
+
+
+def test_mac_range_rejected(L):
+    from paper_1908_10863_amd import fmmlm
+    for bad in (3, 13):
+        o = fmmlm.Opts()
+        L.fmmlm_default_opts(ctypes.byref(o))
+        o.mac_d2 = bad
+        rc, _ = _plan_rc(L, [0.0], [1.0, 2.0], [0.0], [0.0], [0.5], [0], 4, o)
+        assert rc == -1
 
 
 def test_eval_rejects_null_plan(L):
