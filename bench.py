@@ -19,14 +19,15 @@ if ROOT not in sys.path:
 
 METRIC = "FMM matvecs/sec at N=1M 3-layer p=10 vs plain FP64 GPU FMM at <=1e-5 rel error"
 PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
+PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published), FLOP/s
 
 
 def stage_flops(stats, p, stage):
     """Algorithmic floating-point work of one launch of a stage (see the design notes)."""
-    nc = (p + 1) * (p + 2) // 2
     full = (p + 1) ** 2
     if stage == "m2l":
-        return 8.0 * nc * full * (stats["m2l_free_pairs"] + stats["m2l_reaction_pairs"])
+        # dense real-form operator: (p+1)^2 x (p+1)^2 multiply-adds per box pair
+        return 2.0 * full * full * (stats["m2l_free_pairs"] + stats["m2l_reaction_pairs"])
     if stage == "p2p_free":
         return 11.0 * stats["p2p_free_pairs"]
     if stage == "p2p_reaction":
@@ -38,6 +39,38 @@ def stage_flops(stats, p, stage):
     return 0.0
 
 
+def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev):
+    """Plan one form, time `steps` evaluations (HIP events per stage), return stats."""
+    import torch
+    plan = fmmlm.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p, leaf_cap=cap,
+                      precision=precision, mac_d2=mac)
+    st = plan.stats()
+    tag = "fp32" if precision else "fp64"
+    print(f"[bench] {tag}: plan {st['plan_seconds']:.2f}s boxes={st['n_boxes']} "
+          f"m2l={st['m2l_free_pairs']}+{st['m2l_reaction_pairs']} p2p={st['p2p_free_pairs']}",
+          file=sys.stderr, flush=True)
+    q = torch.tensor(w["q"][0], dtype=torch.float64, device=dev)
+    out = torch.empty_like(q)
+    for _ in range(warmup):
+        plan.eval(q, out=out)
+    torch.cuda.synchronize()
+    plan.profile_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval(q, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, nrec = plan.profile_end()
+    phi = out.cpu().numpy()
+    plan.close()
+    avg = {k: v / max(nrec, 1) for k, v in stage_ms.items()}
+    print(f"[bench] {tag}: {steps / elapsed:.2f} matvec/s, stages(ms) " +
+          ", ".join(f"{k}={v:.3f}" for k, v in avg.items()), file=sys.stderr, flush=True)
+    return {"value": steps / elapsed, "ms": 1e3 * elapsed / steps, "stages": avg, "stats": st,
+            "phi": phi}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,7 +78,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--p", type=int, default=None)
-    ap.add_argument("--leaf-cap", type=int, default=None)
+    ap.add_argument("--leaf-cap", type=int, default=128)
+    ap.add_argument("--leaf-cap-fp64", type=int, default=128)
+    ap.add_argument("--mac", type=int, default=4)
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle targets for the CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -60,68 +95,55 @@ def main():
 
     w = workloads.config(args.workload)
     p = args.p or w["p"]
-    cap = args.leaf_cap or 64
     dev = torch.device("cuda:0")
-    print(f"[bench] workload {w['name']} N={len(w['x'])} p={p} leaf_cap={cap}", file=sys.stderr,
-          flush=True)
-    plan = fmmlm.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p, leaf_cap=cap)
-    st = plan.stats()
-    print(f"[bench] plan {st['plan_seconds']:.2f}s boxes={st['n_boxes']} m2l={st['m2l_free_pairs']}"
-          f"+{st['m2l_reaction_pairs']} p2p={st['p2p_free_pairs']}", file=sys.stderr, flush=True)
-    q = torch.tensor(w["q"][0], dtype=torch.float64, device=dev)
-    out = torch.empty_like(q)
-    for _ in range(args.warmup):
-        plan.eval(q, out=out)
-    torch.cuda.synchronize()
-    plan.profile_begin(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.eval(q, out=out)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_ms, nrec = plan.profile_end()
-    phi = out.cpu().numpy()
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
-    avg = {k: v / max(nrec, 1) for k, v in stage_ms.items()}
+    n = len(w["x"])
+    print(f"[bench] workload {w['name']} N={n} p={p} mac={args.mac}", file=sys.stderr, flush=True)
+    base = run_form(fmmlm, w, p, args.leaf_cap_fp64, args.mac, fmmlm.FMMLM_FP64, args.steps,
+                    args.warmup, dev)
+    form = run_form(fmmlm, w, p, args.leaf_cap, args.mac, fmmlm.FMMLM_FP32_COMPENSATED, args.steps,
+                    args.warmup, dev)
+    st = form["stats"]
+    avg = form["stages"]
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
     flops = stage_flops(st, p, dom)
     achieved = flops / (avg[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64 / 1e12), "traffic": None,
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
                 "flops_per_launch": flops, "avg_ms": avg[dom]}
-    print(f"[bench] {value:.2f} matvec/s, stages(ms) " +
-          ", ".join(f"{k}={v:.3f}" for k, v in avg.items()), file=sys.stderr, flush=True)
 
     # CPU baseline: the oracle on a bounded sample of targets of the same workload
     import oracle
     rng = np.random.default_rng(0)
-    tgt = np.sort(rng.choice(len(w["x"]), args.cpu_sample, replace=False))
+    tgt = np.sort(rng.choice(n, args.cpu_sample, replace=False))
     c0 = time.perf_counter()
     ref = oracle.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
                            targets=tgt)
     ct = time.perf_counter() - c0
-    n = len(w["x"])
     cpu = {"value": (len(tgt) / n) / ct, "unit": "matvec/s", "cores": oracle.num_threads(),
            "kind": "oracle",
            "sample": f"{len(tgt)} targets x {n} sources, direct sum (image-series reaction "
                      f"kernels), {ct:.1f} s"}
-    err = float(np.linalg.norm(phi[tgt] - ref) / np.linalg.norm(ref))
+    err32 = float(np.linalg.norm(form["phi"][tgt] - ref) / np.linalg.norm(ref))
+    err64 = float(np.linalg.norm(base["phi"][tgt] - ref) / np.linalg.norm(ref))
 
     rec = {
-        "metric": METRIC, "value": value, "unit": "matvec/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w["name"], "n": n, "p": p, "layers": 3, "leaf_cap": cap,
-                   "precision": "fp64", "rhs": 1},
+        "metric": METRIC, "value": form["value"], "unit": "matvec/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": form["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n": n, "p": p, "layers": 3, "leaf_cap": args.leaf_cap,
+                   "mac_d2": args.mac, "precision": "fp32-compensated (fp64 top 3 levels)",
+                   "rhs": 1},
         "roofline": roofline, "cpu_baseline": cpu,
-        "rel_error_vs_oracle": err,
+        "rel_error_vs_oracle": err32,
+        "fp64_baseline": {"value": base["value"], "ms_per_step": base["ms"],
+                          "leaf_cap": args.leaf_cap_fp64, "rel_error_vs_oracle": err64,
+                          "stage_ms": base["stages"]},
+        "speedup_vs_fp64": form["value"] / base["value"],
         "stage_ms": avg, "plan_seconds": st["plan_seconds"],
         "counts": {k: st[k] for k in ("n_boxes", "n_leaves", "m2l_free_pairs", "m2l_reaction_pairs",
                                       "p2p_free_pairs", "p2p_reaction_pairs", "max_level")},
     }
-    plan.close()
     print(json.dumps(rec))
 
 

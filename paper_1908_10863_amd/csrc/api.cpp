@@ -485,6 +485,83 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->n_free_ops = nfreeops;
     P->nops = nfreeops + (int64_t)B.reac_task.size();
   }
+  // ---- M2L tiles: up to tile_cols target boxes of one level, tree and octant
+  // class per tile (boxes of one class share their interaction offsets); one
+  // step per operator (free space or reaction) present in the tile
+  std::vector<int32_t> tptr(1, 0), ttgt, tlev, sop, skind, ssrc, us, tuptr;
+  {
+    {
+      const int nr0 = (P->p + 1) * (P->p + 1);
+      const int mr0 = (nr0 + 31) / 32;
+      P->mrt = (mr0 + 1) / 2 * 2;
+      if (P->mrt < 2) P->mrt = 2;
+      P->nrk = (nr0 + 15) / 16 * 16;
+      P->tile_cols = (P->mrt <= 4) ? 128 : 64;
+    }
+    const int TBc = P->tile_cols;
+    const int nfo = (int)P->n_free_ops;
+    std::vector<int> slot(std::max<int64_t>(P->nops, 1), -1);
+    std::vector<int> used;
+    for (int l = 0; l <= P->maxlev; ++l) {
+      std::vector<std::vector<int32_t>> bucket((size_t)nt * 8);
+      for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
+        if (mptr[b + 1] > mptr[b]) {
+          const HBox& bx = B.boxes[b];
+          bucket[(size_t)bx.tree * 8 + ((bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2))].push_back(
+              (int32_t)b);
+        }
+      for (const auto& tg : bucket)
+        for (size_t c0 = 0; c0 < tg.size(); c0 += TBc) {
+          const size_t nc_ = std::min<size_t>(TBc, tg.size() - c0);
+          tlev.push_back(l);
+          for (size_t c = 0; c < (size_t)TBc; ++c) ttgt.push_back(c < nc_ ? tg[c0 + c] : -1);
+          used.clear();
+          std::vector<std::vector<int32_t>> cols;
+          for (size_t c = 0; c < nc_; ++c) {
+            const int32_t b = tg[c0 + c];
+            for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
+              const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
+              if (slot[op] < 0) {
+                slot[op] = (int)cols.size();
+                cols.emplace_back(TBc, -1);
+                used.push_back(op);
+              }
+              cols[slot[op]][c] = msrc[e];
+            }
+          }
+          std::sort(used.begin(), used.end());
+          for (int op : used) {
+            sop.push_back(op);
+            skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
+            ssrc.insert(ssrc.end(), cols[slot[op]].begin(), cols[slot[op]].end());
+          }
+          for (int op : used) slot[op] = -1;
+          tptr.push_back((int32_t)sop.size());
+        }
+    }
+    P->ntiles = (int64_t)tlev.size();
+    P->nsteps = (int64_t)sop.size();
+    P->tile_split = 0;
+    while (P->tile_split < P->ntiles && tlev[P->tile_split] < P->opts.fp64_top_levels) ++P->tile_split;
+    // work units of at most kStepsPerUnit steps
+    constexpr int kStepsPerUnit = 16;
+    tuptr.assign(1, 0);
+    for (int64_t t = 0; t < P->ntiles; ++t) {
+      for (int32_t a = tptr[t]; a < tptr[t + 1]; a += kStepsPerUnit) {
+        us.push_back(a);
+        us.push_back(std::min(a + kStepsPerUnit, tptr[t + 1]));
+      }
+      tuptr.push_back((int32_t)(us.size() / 2));
+      if (t + 1 == P->tile_split) P->unit_split = (int64_t)(us.size() / 2);
+    }
+    P->nunits = (int64_t)(us.size() / 2);
+    // operator tables must fit a budget (FP64 + FP32 copies)
+    const double tbytes = (double)P->nops * P->nrk * 32.0 * P->mrt * (P->fp32 ? 12.0 : 8.0);
+    if (tbytes > 32.0 * (1 << 30)) {
+      set_last_error("M2L operator tables exceed 32 GiB");
+      return FMMLM_ENOMEM;
+    }
+  }
   // ---- P2P CSR over leaves
   std::vector<int32_t> pptr(P->nleaves + 1, 0), psrc;
   std::vector<int32_t> rptr(P->nleaves + 1, 0), rsrc;
@@ -558,6 +635,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
   UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
   UP(coefA, coefA); UP(sc_levels, scl);
+  UP(tile_ptr, tptr); UP(tile_tgt, ttgt); UP(tile_level, tlev); UP(step_op, sop); UP(step_src, ssrc);
+  UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind);
+  if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) return rc;
 #undef UP
   // ---- operators: free-space harmonics and reaction Sommerfeld tables
   if ((rc = dev_alloc(P, &P->G, (size_t)std::max<int64_t>(P->nops, 1) * P->ng * 2))) return rc;
@@ -573,6 +653,19 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   rc = gpu_build_ops(P, B.free_off, B.reac_task, B.reac_phi, B.reac_S, tables, st);
   hipFree(tables);
   if (rc) return rc;
+  if ((rc = dev_alloc(P, &P->Tfree, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;
+  if ((rc = gpu_build_real_ops(P, st))) return rc;
+  if (P->fp32) {
+    const size_t nr = (size_t)(P->p + 1) * (P->p + 1);
+    if ((rc = dev_alloc(P, &P->Tfree32, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;
+    if ((rc = dev_alloc(P, &P->M32, (size_t)P->NB * nr))) return rc;
+    if ((rc = dev_alloc(P, &P->qt32, P->NP))) return rc;
+    if ((rc = dev_alloc(P, &P->pxh, P->NP)) || (rc = dev_alloc(P, &P->pxl, P->NP)) ||
+        (rc = dev_alloc(P, &P->pyh, P->NP)) || (rc = dev_alloc(P, &P->pyl, P->NP)) ||
+        (rc = dev_alloc(P, &P->phh, P->NP)) || (rc = dev_alloc(P, &P->phl, P->NP)))
+      return rc;
+    if ((rc = gpu_build_fp32(P, st))) return rc;
+  }
   P->stats.n_free_ops = P->n_free_ops;
   P->stats.n_reaction_ops = (int64_t)B.reac_task.size();
   P->stats.n_sommerfeld_tasks = (int64_t)B.tasks.size();
@@ -596,8 +689,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   // ---- workspace
   if ((rc = dev_alloc(P, &P->qt, P->NP))) return rc;
   if ((rc = dev_alloc(P, &P->phit, P->NP))) return rc;
-  if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * P->nc * 2))) return rc;
-  if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * P->nc * 2))) return rc;
+  if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * (P->p + 1) * (P->p + 1)))) return rc;
+  if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * (P->p + 1) * (P->p + 1)))) return rc;
   FMM_HIP_TRY(hipStreamSynchronize(st));
   return FMMLM_OK;
 }
@@ -637,7 +730,7 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   if (o.precision != FMMLM_FP64 && o.precision != FMMLM_FP32_COMPENSATED) return FMMLM_EINVAL;
   for (int i = 0; i < 3; ++i)
     if (o.reserved[i] != 0) return FMMLM_EINVAL;
-  if (o.precision != FMMLM_FP64) return FMMLM_EUNSUPPORTED;
+  if (o.fp64_top_levels < 0 || o.fp64_top_levels > kMaxLevel + 1) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::vector<double> dv, ev, X, Y, Z;
   std::vector<int32_t> LAY;
@@ -669,6 +762,7 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   P->nc = ncoef(p);
   P->ng = ncoef(2 * p);
   P->opts = o;
+  P->fp32 = (o.precision == FMMLM_FP32_COMPENSATED);
   try {
     rc = build_plan(P, X, Y, Z, LAY, st);
   } catch (const std::bad_alloc&) {

@@ -106,6 +106,25 @@ struct fmmlm_plan_s {
   int32_t *m2l_nfree = nullptr;    // [NB] number of free entries per target box
   int32_t *m2l_src = nullptr, *m2l_op = nullptr;  // op < 0 encodes mirrored source: ~op
   double* G = nullptr;             // operators [nops][ng] complex (re, im interleaved)
+  // free-space M2L as GEMMs over tiles of target boxes
+  double* Tfree = nullptr;         // [nops][nrk][32 mrt] real-form operators (free space, then reaction)
+  int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
+  int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
+  int64_t tile_split = 0;          // tiles [0, tile_split) are on levels kept in FP64
+  // work units: a tile's steps split into chunks (more blocks in flight)
+  int64_t nunits = 0, unit_split = 0;
+  int32_t *unit_s = nullptr;       // [2 * nunits] step range of each unit
+  int32_t *tile_unit_ptr = nullptr;// [ntiles + 1]
+  double* Wm2l = nullptr;          // [nunits][tile_cols][32 mrt] partial products
+  // FP32 form
+  bool fp32 = false;
+  float* Tfree32 = nullptr;        // FP32 copy of Tfree
+  float* M32 = nullptr;            // FP32 copy of the multipole expansions (GEMM operand)
+  float *pxh = nullptr, *pxl = nullptr, *pyh = nullptr, *pyl = nullptr, *phh = nullptr, *phl = nullptr;
+  float* qt32 = nullptr;
+  int64_t ntiles = 0, nsteps = 0;
+  int32_t *tile_ptr = nullptr, *tile_tgt = nullptr, *tile_level = nullptr;
+  int32_t *step_op = nullptr, *step_src = nullptr, *step_kind = nullptr;
   int64_t nops = 0, n_free_ops = 0;
   // P2P free, CSR over leaves
   int32_t *p2p_ptr = nullptr;      // [nleaves + 1]
@@ -120,7 +139,7 @@ struct fmmlm_plan_s {
   double *coefC2inv = nullptr;     // 1 / c_n^2, n <= p
   // workspace
   double *qt = nullptr, *phit = nullptr;
-  double *M = nullptr, *Lx = nullptr;  // [NB][nc] complex
+  double *M = nullptr, *Lx = nullptr;  // [NB][(p+1)^2] real layout
   double *sc_levels = nullptr;     // 1/S_l per level
   // live stage timing
   std::vector<hipEvent_t> prof_ev;  // [max_evals][FMMLM_NSTAGES + 1]
@@ -162,6 +181,8 @@ double zeta_inf(const Medium& md, int lt, int ls, int a, int b);
 int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
                   const std::vector<int>& reac_task, const std::vector<double>& reac_phi,
                   const std::vector<double>& reac_S, const double* d_tables, hipStream_t st);
+int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
+int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
 int gpu_eval_one(fmmlm_plan_s* P, const double* q, double* phi, uint32_t parts, hipStream_t st,
                  hipEvent_t* ev);
 
