@@ -62,7 +62,12 @@ typedef struct {
   int32_t leaf_cap;        /* a box is split while it holds more points (default 64) */
   int32_t precision;       /* FMMLM_FP64 (default) or FMMLM_FP32_COMPENSATED */
   int32_t fp64_top_levels; /* FP32 form: tree levels 0..k-1 kept in FP64 (default 3) */
-  int32_t max_rhs;         /* largest nrhs accepted by eval (default 64) */
+  int32_t max_rhs;         /* largest nrhs accepted by eval (default 1).  Above 1 the plan
+                              holds expansions for G = min(max_rhs, 64) charge vectors and
+                              evaluates them together (batched M2L on the matrix cores in
+                              the FP32 form, one 1/r per pair for all vectors in P2P);
+                              device memory grows by about G times the single-vector
+                              expansion and point arrays */
   int32_t mac_d2;          /* multipole acceptance: two same-level boxes exchange expansions
                               only if their centres are at least sqrt(mac_d2) box sizes apart
                               (and not adjacent); 4 is the classic one-box separation.
@@ -105,7 +110,8 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
 /*
  * One matrix-vector product per charge vector: phi = G q (eq. totalinteraction).
  *
- *  nrhs           1..opts.max_rhs charge vectors
+ *  nrhs           1..opts.max_rhs charge vectors, evaluated together in passes of
+ *                 G = min(max_rhs, 64)
  *  q              device, q[r * ldq + j] for r < nrhs, j < n (user order, FP64)
  *  ldq            >= n
  *  phi            device, phi[r * ldphi + i], overwritten (FP64)

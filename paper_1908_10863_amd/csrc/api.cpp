@@ -658,7 +658,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (P->fp32) {
     const size_t nr = (size_t)(P->p + 1) * (P->p + 1);
     if ((rc = dev_alloc(P, &P->Tfree32, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;
-    if ((rc = dev_alloc(P, &P->M32, (size_t)P->NB * nr))) return rc;
+    if (std::min(P->opts.max_rhs, 64) == 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nr))) return rc;
     if ((rc = dev_alloc(P, &P->qt32, P->NP))) return rc;
     if ((rc = dev_alloc(P, &P->pxh, P->NP)) || (rc = dev_alloc(P, &P->pxl, P->NP)) ||
         (rc = dev_alloc(P, &P->pyh, P->NP)) || (rc = dev_alloc(P, &P->pyl, P->NP)) ||
@@ -686,11 +686,27 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     hipFree(dc);
     if (rc) return rc;
   }
-  // ---- workspace
-  if ((rc = dev_alloc(P, &P->qt, P->NP))) return rc;
-  if ((rc = dev_alloc(P, &P->phit, P->NP))) return rc;
-  if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * (P->p + 1) * (P->p + 1)))) return rc;
-  if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * (P->p + 1) * (P->p + 1)))) return rc;
+  // ---- workspace (G = min(max_rhs, 64) vectors per pass)
+  P->gmax = std::min(P->opts.max_rhs, 64);
+  const size_t G = (size_t)P->gmax;
+  const size_t nrr = (size_t)(P->p + 1) * (P->p + 1);
+  if ((rc = dev_alloc(P, &P->qt, P->NP * G))) return rc;
+  if ((rc = dev_alloc(P, &P->phit, P->NP * G))) return rc;
+  if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
+  if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
+  if (P->fp32 && G > 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nrr * G))) return rc;
+  if (G > 1) {
+    if ((rc = dev_alloc(P, &P->qb64, P->NP * 64))) return rc;
+    if (P->fp32 && (rc = dev_alloc(P, &P->qb32, P->NP * 64))) return rc;
+    std::vector<int32_t> bb;
+    for (int64_t b = 0; b < P->NB; ++b)
+      if (mptr[b + 1] > mptr[b]) {
+        if (B.boxes[b].level < P->opts.fp64_top_levels) P->bbox_split = (int64_t)bb.size() + 1;
+        bb.push_back((int32_t)b);
+      }
+    P->nbbox = (int64_t)bb.size();
+    if ((rc = dev_upload(P, &P->bbox, bb, st))) return rc;
+  }
   FMM_HIP_TRY(hipStreamSynchronize(st));
   return FMMLM_OK;
 }
@@ -708,7 +724,7 @@ void fmmlm_default_opts(fmmlm_opts* o) {
   o->leaf_cap = 64;
   o->precision = FMMLM_FP64;
   o->fp64_top_levels = 3;
-  o->max_rhs = 64;
+  o->max_rhs = 1;
   o->mac_d2 = 6;
 }
 
@@ -797,10 +813,16 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   if (ldq < plan->N || ldphi < plan->N) return FMMLM_EINVAL;
   if (parts == 0 || (parts & ~(FMMLM_FREE | FMMLM_REACTION))) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  for (int r = 0; r < nrhs; ++r) {
+  if (nrhs == 1) {
     hipEvent_t* ev = nullptr;
     if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
-    int rc = gpu_eval_one(plan, q + (int64_t)r * ldq, phi + (int64_t)r * ldphi, parts, st, ev);
+    return gpu_eval_one(plan, q, phi, parts, st, ev);
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += plan->gmax) {
+    const int g = std::min(plan->gmax, nrhs - r0);
+    hipEvent_t* ev = nullptr;
+    if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
+    int rc = gpu_eval_batch(plan, g, q + (int64_t)r0 * ldq, ldq, phi + (int64_t)r0 * ldphi, ldphi, parts, st, ev);
     if (rc) return rc;
   }
   return FMMLM_OK;

@@ -122,6 +122,13 @@ struct fmmlm_plan_s {
   float* M32 = nullptr;            // FP32 copy of the multipole expansions (GEMM operand)
   float *pxh = nullptr, *pxl = nullptr, *pyh = nullptr, *pyl = nullptr, *phh = nullptr, *phl = nullptr;
   float* qt32 = nullptr;
+  // batched form (opts.max_rhs > 1): expansions, charges and potentials of up
+  // to G = min(max_rhs, 64) vectors; M2L one block per target box
+  int gmax = 1;
+  int64_t nbbox = 0, bbox_split = 0;
+  int32_t* bbox = nullptr;         // target boxes with M2L entries, level order
+  double* qb64 = nullptr;          // [NP][64] vector-minor charges (FP64)
+  float* qb32 = nullptr;           // [NP][64] (FP32 form)
   int64_t ntiles = 0, nsteps = 0;
   int32_t *tile_ptr = nullptr, *tile_tgt = nullptr, *tile_level = nullptr;
   int32_t *step_op = nullptr, *step_src = nullptr, *step_kind = nullptr;
@@ -183,6 +190,8 @@ int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
                   const std::vector<double>& reac_S, const double* d_tables, hipStream_t st);
 int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
+int gpu_eval_batch(fmmlm_plan_s* P, int g, const double* q, int64_t ldq, double* phi, int64_t ldphi,
+                   uint32_t parts, hipStream_t st, hipEvent_t* ev);
 int gpu_eval_one(fmmlm_plan_s* P, const double* q, double* phi, uint32_t parts, hipStream_t st,
                  hipEvent_t* ev);
 

@@ -121,7 +121,7 @@ class Plan:
     """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
 
     def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
-                 fp64_top_levels=3, max_rhs=64, mac_d2=None, stream=None):
+                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None):
         self.d = _host(d, np.float64)
         self.eps = _host(eps, np.float64)
         x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)

@@ -41,7 +41,7 @@ def test_default_opts(L):
     from paper_1908_10863_amd import fmmlm
     o = fmmlm.Opts()
     L.fmmlm_default_opts(ctypes.byref(o))
-    assert (o.leaf_cap, o.precision, o.fp64_top_levels, o.max_rhs, o.mac_d2) == (64, 0, 3, 64, 6)
+    assert (o.leaf_cap, o.precision, o.fp64_top_levels, o.max_rhs, o.mac_d2) == (64, 0, 3, 1, 6)
 
 
 def test_strerror_never_null(L):

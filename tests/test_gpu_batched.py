@@ -1,0 +1,106 @@
+"""GPU parity of the batched form (many charge vectors per evaluation): equality with
+single-vector evaluations, linearity, and the FP64 oracle at small and full size
+(the four-layer workload with 64 vectors, N = 524288)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1908_10863_amd import fmmlm
+    fmmlm.lib()
+    return fmmlm
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_single(dev, F, precision):
+    """nrhs = 70 (two passes of 64 and 6) against 70 single-vector evaluations."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say(f"batched == single precision={precision}")
+    w = W.config(3, n=3000)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=8, leaf_cap=40,
+                  precision=precision, max_rhs=70)
+    rng = np.random.default_rng(4)
+    Q = torch.tensor(rng.uniform(-1, 1, (70, 3000)), dtype=torch.float64, device=dev)
+    both = plan.eval(Q).cpu().numpy()
+    tol = 1e-12 if precision == 0 else 2e-6
+    for r in (0, 1, 37, 63, 64, 69):
+        one = plan.eval(Q[r].contiguous()).cpu().numpy()
+        assert relerr(both[r], one) < tol, r
+    # linearity across the batch
+    lin = plan.eval((Q[0] + 2.0 * Q[5]).contiguous()).cpu().numpy()
+    assert relerr(both[0] + 2.0 * both[5], lin) < tol
+    plan.close()
+
+
+def test_batched_fp32_vs_oracle_small(dev, F, oracle_mod):
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say("batched fp32 vs oracle (four layers, N=2000)")
+    w = W.config(3, n=2000)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=32,
+                  precision=F.FMMLM_FP32_COMPENSATED, max_rhs=64, mac_d2=4)
+    Q = torch.tensor(w["q"], dtype=torch.float64, device=dev)
+    phi = plan.eval(Q).cpu().numpy()
+    plan.close()
+    t = np.arange(0, 2000, 9)
+    for r in (0, 31, 63):
+        ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][r],
+                                   targets=t, method="quad")
+        e = relerr(phi[r][t], ref)
+        _say(f"  vector {r}: {e:.3e}")
+        assert e <= 1e-5
+
+
+def test_batched_full_size_sampled(dev, F, oracle_mod):
+    """Workload 4 at full size: 64 vectors in one evaluation, FP32 form; one vector
+    checked against the direct-sum oracle (quadrature kernels) at 4 targets, every
+    vector against the FP64 single-vector path on 2048 sampled outputs."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say("batched full size")
+    w = W.config(3)
+    n = len(w["x"])
+    Q = torch.tensor(w["q"], dtype=torch.float64, device=dev)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=128,
+                  precision=F.FMMLM_FP32_COMPENSATED, max_rhs=64, mac_d2=4)
+    phi = plan.eval(Q).cpu().numpy()
+    plan.close()
+    rng = np.random.default_rng(77)
+    t = np.sort(rng.choice(n, 4, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                               targets=t, method="quad")
+    e = relerr(phi[0][t], ref)
+    _say(f"  vector 0 vs oracle at 4 targets: {e:.3e}")
+    assert e <= 1e-5
+    p64 = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=128, mac_d2=4)
+    s = np.sort(rng.choice(n, 2048, replace=False))
+    worst = 0.0
+    for r in (0, 17, 42, 63):
+        one = p64.eval(Q[r].contiguous()).cpu().numpy()
+        worst = max(worst, relerr(phi[r][s], one[s]))
+    p64.close()
+    _say(f"  batched fp32 vs single fp64: {worst:.3e}")
+    assert worst <= 5e-6

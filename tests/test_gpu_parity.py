@@ -301,13 +301,14 @@ def test_multiple_rhs_and_determinism(dev, F):
     from paper_1908_10863_amd import workloads as W
     _say("multi rhs")
     w = W.config(0, n=600)
-    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=6, leaf_cap=30)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=6, leaf_cap=30, max_rhs=3)
     rng = np.random.default_rng(1)
     Q = torch.tensor(rng.uniform(-1, 1, (3, 600)), dtype=torch.float64, device=dev)
     both = plan.eval(Q).cpu().numpy()
     for r in range(3):
         one = plan.eval(Q[r].contiguous()).cpu().numpy()
-        assert np.array_equal(one, both[r])
+        # batched and single-vector passes sum in different orders
+        np.testing.assert_allclose(both[r], one, rtol=0, atol=1e-13 * np.abs(one).max())
     again = plan.eval(Q).cpu().numpy()
     assert np.array_equal(again, both)
     # linearity
