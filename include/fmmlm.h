@@ -154,6 +154,11 @@ typedef struct {
   double x0, y0;               /* common xy origin */
   double plan_seconds;         /* wall time of fmm_layered_plan */
   int64_t device_bytes;        /* device memory held by the plan */
+  double tree_seconds;         /* plan phases: anchored trees, Morton keys and sort */
+  double lists_seconds;        /*   boxes, interaction lists, M2L tiles, P2P lists */
+  double ops_seconds;          /*   M2L operators (free and reaction, incl. table_seconds) */
+  double table_seconds;        /*   Sommerfeld initial values + recurrence of the reaction M2L */
+  double nearfield_seconds;    /*   reaction near-field kernel values */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
@@ -171,9 +176,12 @@ int fmm_layered_plan_tree(fmmlm_plan_t plan, int32_t t, int32_t* layer, int32_t*
 /*
  * The scaled Sommerfeld-type integrals S^N I^{ab}_{N,M}(rho, z) of
  * eq. scaledsommerfeldint for 0 <= M <= N <= nmax, computed on the GPU the
- * way plans compute them: 4 nmax + 1 initial values (M = 0, 1) by quadrature
- * (real axis, or the K_M contour form of eq. contourchange when rho exceeds
- * z plus the density's decay length), the rest by eq. recurrence.
+ * way plans compute them: 4 nmax + 1 initial values (M = 0, 1), the rest by
+ * eq. recurrence.  An initial value is the leading term sinf e^{-k zinf} of the
+ * density (fmm_layered_density_asymptotic) integrated in closed form, plus the
+ * remainder by quadrature (real axis, or the K_M contour form of
+ * eq. contourchange when rho exceeds z + zinf + 2 dmin, the remainder's decay
+ * length).
  *
  *  medium         n_interfaces, z_interfaces [L], eps [L+1] (host); n_interfaces = 0
  *                 selects sigma == 1
@@ -188,6 +196,20 @@ int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, con
                            int32_t lt, int32_t ls, int32_t a, int32_t b, double S, int64_t npts,
                            const double* rho, const double* z, int32_t nmax, double* out,
                            void* hip_stream);
+
+/*
+ * Leading term of a reaction density as k -> infinity (eq. densityasymptotic):
+ * sigma^{ab}_{lt,ls}(k) = sinf e^{-k zinf} (1 + O(e^{-2 k dmin})), dmin the
+ * thinnest finite layer.  zinf is the shortest ray path from the source's exit
+ * interface to the target's entry interface, sinf the product of the local
+ * reflection/transmission coefficients along it.  Host computation (no GPU).
+ *
+ *  sinf, zinf     host scalars, written on success
+ *  errors         FMMLM_EINVAL (null pointer, invalid component), medium errors
+ */
+int fmm_layered_density_asymptotic(int32_t n_interfaces, const double* z_interfaces,
+                                   const double* eps, int32_t lt, int32_t ls, int32_t a, int32_t b,
+                                   double* sinf, double* zinf);
 
 /*
  * Reaction densities sigma^{ab}_{lt,ls}(k) of App. A at complex k (Re k >= 0),

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <unordered_set>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -93,6 +94,16 @@ int fetch(const T* src, int64_t n, std::vector<T>& dst) {
     std::memcpy(dst.data(), src, n * sizeof(T));
   }
   return FMMLM_OK;
+}
+
+inline uint64_t spread1by2(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
 }
 
 inline int compact1by2(uint64_t v) {
@@ -282,6 +293,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
                const std::vector<double>& Z, const std::vector<int32_t>& LAY, hipStream_t st) {
   const int L = P->L;
   const int64_t N = P->N;
+  auto tphase = std::chrono::steady_clock::now();
   // ---- anchored trees (layer, side) with members in user order
   std::vector<std::vector<int64_t>> members(L + 1);
   for (int64_t i = 0; i < N; ++i) members[LAY[i]].push_back(i);
@@ -350,6 +362,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   hipFree(dy);
   hipFree(dz);
   P->NP = off;
+  P->stats.tree_seconds = seconds_since(tphase);
+  tphase = std::chrono::steady_clock::now();
   // ---- boxes, level by level over all trees (level-major global order)
   Builder B;
   B.P = P;
@@ -363,11 +377,73 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     per_level[0].push_back((int)B.boxes.size());
     B.boxes.push_back(r);
   }
+  // A box is split when it holds more than cap points, and also when a box
+  // that the traversal would pair with it at this level (free: same tree,
+  // adjacent or inside the MAC; reaction: any tree, touching-interface
+  // adjacency or inside the MAC in the mirrored frame) holds more than
+  // kBalance * cap points.  Without the second rule a sparse leaf would take
+  // the P2P of a whole dense subtree next to it (unbounded pair counts when
+  // densities differ across layers or clusters); with it a leaf's P2P partner
+  // holds at most kBalance * cap points.
+  constexpr int64_t kBalance = 8;
+  const int mac = P->opts.mac_d2;
+  std::vector<char> free_tree(nt);
+  for (int t = 0; t < nt; ++t) {
+    const TreeInfo& T = P->trees[t];
+    free_tree[t] = (T.layer <= L - 1) ? (T.side == 1) : (T.side == 2);
+  }
+  auto cell = [](int ix, int iy, int ih) {
+    return spread1by2((uint64_t)ix) | (spread1by2((uint64_t)iy) << 1) | (spread1by2((uint64_t)ih) << 2);
+  };
   for (int l = 0;; ++l) {
     std::vector<int> next;
-    for (int b : per_level[l]) {
+    std::vector<char> split(per_level[l].size(), 0);
+    if (l < kMaxLevel) {
+      std::unordered_set<uint64_t> heavy_reac;               // cells (any tree), ih <= 2
+      std::vector<std::unordered_set<uint64_t>> heavy_free(nt);
+      for (size_t k = 0; k < per_level[l].size(); ++k) {
+        const HBox& bx = B.boxes[per_level[l][k]];
+        if (bx.count <= cap) continue;
+        split[k] = 1;
+        if (bx.count <= kBalance * cap) continue;
+        if (compact1by2(bx.prefix >> 2) <= 2) heavy_reac.insert(bx.prefix);
+        if (free_tree[bx.tree]) heavy_free[bx.tree].insert(bx.prefix);
+      }
+      const int n1d = 1 << l;
+      for (size_t k = 0; k < per_level[l].size(); ++k) {
+        if (split[k]) continue;
+        const HBox& bx = B.boxes[per_level[l][k]];
+        const int ix = compact1by2(bx.prefix), iy = compact1by2(bx.prefix >> 1), ih = compact1by2(bx.prefix >> 2);
+        bool hit = false;
+        for (int dx = -3; dx <= 3 && !hit; ++dx)
+          for (int dy = -3; dy <= 3 && !hit; ++dy) {
+            const int jx = ix + dx, jy = iy + dy;
+            if (jx < 0 || jy < 0 || jx >= n1d || jy >= n1d) continue;
+            if (!heavy_reac.empty()) {
+              for (int jh = 0; jh <= 2 && !hit; ++jh) {
+                const int dz = ih + jh + 1;
+                const bool near = (std::abs(dx) <= 1 && std::abs(dy) <= 1 && dz == 1) ||
+                                  dx * dx + dy * dy + dz * dz < mac;
+                if (near && heavy_reac.count(cell(jx, jy, jh))) hit = true;
+              }
+            }
+            if (free_tree[bx.tree] && !heavy_free[bx.tree].empty()) {
+              for (int dz = -3; dz <= 3 && !hit; ++dz) {
+                const int jh = ih + dz;
+                if (jh < 0 || jh >= n1d) continue;
+                const bool near = (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) ||
+                                  dx * dx + dy * dy + dz * dz < mac;
+                if (near && heavy_free[bx.tree].count(cell(jx, jy, jh))) hit = true;
+              }
+            }
+          }
+        split[k] = hit;
+      }
+    }
+    for (size_t k = 0; k < per_level[l].size(); ++k) {
+      const int b = per_level[l][k];
       const HBox parent = B.boxes[b];  // copy: the vector grows below
-      if (parent.count <= cap || l >= kMaxLevel) continue;
+      if (!split[k]) continue;
       const TreeInfo& T = P->trees[parent.tree];
       const int shift = 3 * (20 - l);
       int64_t i = parent.start;
@@ -415,13 +491,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   std::vector<CompInfo> comps;
   for (int t = 0; t < nt; ++t)
     for (int s = 0; s < nt; ++s) {
-      CompInfo c;
-      c.lt = P->trees[t].layer;
-      c.a = P->trees[t].side;
-      c.ls = P->trees[s].layer;
-      c.b = P->trees[s].side;
-      c.zinf = zeta_inf(P->medium, c.lt, c.ls, c.a, c.b);
-      comps.push_back(c);
+      comps.push_back(make_comp(P->medium, P->trees[t].layer, P->trees[s].layer, P->trees[t].side,
+                                P->trees[s].side));
     }
   for (int t = 0; t < nt; ++t)
     for (int s = 0; s < nt; ++s) B.process_reac(B.root[t], B.root[s], t * nt + s);
@@ -639,12 +710,16 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind);
   if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) return rc;
 #undef UP
+  P->stats.lists_seconds = seconds_since(tphase);
+  tphase = std::chrono::steady_clock::now();
   // ---- operators: free-space harmonics and reaction Sommerfeld tables
   if ((rc = dev_alloc(P, &P->G, (size_t)std::max<int64_t>(P->nops, 1) * P->ng * 2))) return rc;
   double* tables = nullptr;
   if (!B.tasks.empty()) {
     FMM_HIP_TRY(hipMalloc(&tables, B.tasks.size() * (size_t)P->ng * sizeof(double)));
+    const auto ts = std::chrono::steady_clock::now();
     rc = gpu_sommerfeld_tables(P->medium, comps, B.tasks, 2 * p, tables, st);
+    P->stats.table_seconds = seconds_since(ts);
     if (rc) {
       hipFree(tables);
       return rc;
@@ -669,6 +744,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   P->stats.n_free_ops = P->n_free_ops;
   P->stats.n_reaction_ops = (int64_t)B.reac_task.size();
   P->stats.n_sommerfeld_tasks = (int64_t)B.tasks.size();
+  P->stats.ops_seconds = seconds_since(tphase);
   // ---- reaction near field values
   const int64_t npairs = (int64_t)rp_t.size();
   if ((rc = dev_alloc(P, &P->rp_val, (size_t)npairs))) return rc;
@@ -680,7 +756,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     FMM_HIP_TRY(hipMemcpyAsync(dt, rp_t.data(), npairs * 4, hipMemcpyHostToDevice, st));
     FMM_HIP_TRY(hipMemcpyAsync(ds, rp_s.data(), npairs * 4, hipMemcpyHostToDevice, st));
     FMM_HIP_TRY(hipMemcpyAsync(dc, rp_c.data(), npairs * 4, hipMemcpyHostToDevice, st));
+    const auto ts = std::chrono::steady_clock::now();
     rc = gpu_reaction_nearfield(P->medium, comps, dt, ds, dc, npairs, P->px, P->py, P->ph, P->rp_val, st);
+    P->stats.nearfield_seconds = seconds_since(ts);
     hipFree(dt);
     hipFree(ds);
     hipFree(dc);
@@ -893,7 +971,7 @@ int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, con
       return FMMLM_EINVAL;
   }
   std::vector<CompInfo> comps(1);
-  comps[0] = CompInfo{lt, ls, a, b, zeta_inf(md, lt, ls, a, b)};
+  comps[0] = make_comp(md, lt, ls, a, b);
   std::vector<SommTask> tasks(npts);
   for (int64_t i = 0; i < npts; ++i) {
     if (!(rho[i] >= 0.0) || !(z[i] > 0.0)) return FMMLM_EINVAL;
@@ -927,8 +1005,26 @@ int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const 
   if ((a == 1 && lt > L - 1) || (a == 2 && lt < 1) || (b == 1 && ls > L - 1) || (b == 2 && ls < 1))
     return FMMLM_EINVAL;
   Medium md = make_medium(L, dv.data(), ev.data());
-  CompInfo c{lt, ls, a, b, 0.0};
+  CompInfo c{lt, ls, a, b, 0.0, 0.0};
   return gpu_density(md, c, nk, k_re, k_im, out_re, out_im, static_cast<hipStream_t>(hip_stream));
+}
+
+int fmm_layered_density_asymptotic(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                                   int32_t lt, int32_t ls, int32_t a, int32_t b, double* sinf,
+                                   double* zinf) {
+  if (!sinf || !zinf || !z_interfaces || !eps || n_interfaces < 1) return FMMLM_EINVAL;
+  std::vector<double> dv(z_interfaces, z_interfaces + n_interfaces), ev(eps, eps + n_interfaces + 1);
+  int rc = validate_medium(n_interfaces, dv, ev);
+  if (rc) return rc;
+  const int L = n_interfaces;
+  if (lt < 0 || lt > L || ls < 0 || ls > L || a < 1 || a > 2 || b < 1 || b > 2) return FMMLM_EINVAL;
+  if ((a == 1 && lt > L - 1) || (a == 2 && lt < 1) || (b == 1 && ls > L - 1) || (b == 2 && ls < 1))
+    return FMMLM_EINVAL;
+  Medium md = make_medium(L, dv.data(), ev.data());
+  const CompInfo c = make_comp(md, lt, ls, a, b);
+  *sinf = c.sinf;
+  *zinf = c.zinf;
+  return FMMLM_OK;
 }
 
 int fmm_layered_profile_begin(fmmlm_plan_t plan, int32_t max_evals) {

@@ -172,6 +172,7 @@ struct SommTask {
 struct CompInfo {
   int lt, ls, a, b;
   double zinf;        // decay length of the density (shortest ray path)
+  double sinf;        // its amplitude: sigma(k) e^{k zinf} -> sinf as k -> infinity
 };
 int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,
                           const std::vector<SommTask>& tasks, int nmax, double* d_out,
@@ -183,6 +184,10 @@ int gpu_reaction_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
 int gpu_density(const Medium& md, const CompInfo& c, int64_t nk, const double* kre,
                 const double* kim, double* ore, double* oim, hipStream_t st);
 double zeta_inf(const Medium& md, int lt, int ls, int a, int b);
+double sigma_inf(const Medium& md, int lt, int ls, int a, int b);
+inline CompInfo make_comp(const Medium& md, int lt, int ls, int a, int b) {
+  return CompInfo{lt, ls, a, b, zeta_inf(md, lt, ls, a, b), sigma_inf(md, lt, ls, a, b)};
+}
 
 // fmm.hip
 int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,

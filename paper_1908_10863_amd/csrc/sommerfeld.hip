@@ -167,30 +167,67 @@ __device__ double max_thickness(const Medium& md) {
   return m;
 }
 
+// amp S^n P~_n^m(Z/R) / R^{n+1}, R = sqrt(rho^2 + Z^2), added to o0[n] (m = 0,
+// n <= nmax) and o1[n] (m = 1, 1 <= n <= nmax; o1 may be null).  This is the
+// normalised integral of the density amp e^{-k Zi} at z = Z - Zi (Sec. 3.4:
+// int_0^inf J_m(k rho) k^n e^{-k Z} dk = (n-m)! P_n^m(Z/R) / R^{n+1}, P_n^m without the
+// Condon-Shortley phase), with P~_n^m = sqrt((n-m)!/(n+m)!) P_n^m.
+__device__ void image_values(double amp, double S, double rho, double Z, int nmax, double* o0,
+                             double* o1) {
+  const double R = sqrt(rho * rho + Z * Z);
+  const double x = Z / R, sn = rho / R, t = S / R;
+  double pw = amp / R;
+  double q0 = 0.0, p0 = 1.0;  // P_{n-1}^0, P_n^0
+  double q1 = 0.0, p1 = sn;   // P_{n-1}^1, P_n^1 (n >= 1)
+  for (int n = 0; n <= nmax; ++n) {
+    o0[n] += pw * p0;
+    if (o1 != nullptr && n >= 1) {
+      o1[n] += pw * p1 / sqrt((double)n * (n + 1));
+      const double r1 = ((2.0 * n + 1.0) * x * p1 - (n + 1.0) * q1) / n;
+      q1 = p1;
+      p1 = r1;
+    }
+    const double r0 = ((2.0 * n + 1.0) * x * p0 - n * q0) / (n + 1.0);
+    q0 = p0;
+    p0 = r0;
+    pw *= t;
+  }
+}
+
 // S^n I_{n,0} -> out0[n] (n <= nmax), S^n I_{n,1} -> out1[n] (1 <= n <= nmax).
 // out1 may be null (only m = 0 wanted).  1/sqrt((n+m)!(n-m)!) included.
+// The density's leading term sinf e^{-k zinf} (eq. densityasymptotic) is
+// integrated in closed form by image_values; only the remainder
+// sigma(k) - sinf e^{-k zinf}, which decays like e^{-k (zinf + 2 dmin)}, goes
+// through the quadrature.  With one interface the remainder is zero.
 __device__ void initial_values(const Medium& md, const Scatter& sc, const CompInfo& c, double S,
                                double rho, double z, int nmax, double* out0, double* out1) {
   constexpr int kMaxN = 2 * kPMax + 1;
+  const bool want1 = (out1 != nullptr) && rho > 0.0;
+  for (int n = 0; n <= nmax; ++n) {
+    out0[n] = 0.0;
+    if (out1 != nullptr) out1[n] = 0.0;
+  }
+  image_values(c.sinf, S, rho, z + c.zinf, nmax, out0, want1 ? out1 : nullptr);
+  if (md.L < 2) return;
   double acc0[kMaxN], acc1[kMaxN];
   for (int n = 0; n <= nmax; ++n) acc0[n] = acc1[n] = 0.0;
-  const double zeff = z + c.zinf;
-  const bool contour = (rho > zeff) && (md.L > 0 || rho > z);
   const double dmin = min_thickness(md);
+  const double zq = z + c.zinf + 2.0 * dmin;  // decay length of the remainder
+  const bool contour = rho > zq;
   double small = 1.0;
-  if (zeff < small) small = zeff;
-  if (dmin > 0.0 && dmin < small) small = dmin;
+  if (zq < small) small = zq;
+  if (dmin < small) small = dmin;
   if (contour && rho < small) small = rho;
   Panels pn;
   pn.ratio = 1.25;
   pn.h0 = 1e-3 * small;
-  const bool want1 = (out1 != nullptr) && rho > 0.0;
   if (!contour) {
-    // real axis: J_m(k rho) (kS)^n e^{-kz} sigma(k)
-    pn.kmax = (2.0 * nmax + 50.0) / zeff;
-    double hmax = 2.0 / zeff;
+    // real axis: J_m(k rho) (kS)^n e^{-kz} (sigma(k) - sinf e^{-k zinf})
+    pn.kmax = (2.0 * nmax + 50.0) / zq;
+    double hmax = 2.0 / zq;
     if (rho > 0.0 && 3.14159265358979 / rho < hmax) hmax = 3.14159265358979 / rho;
-    if (dmin > 0.0 && 2.5 * dmin < hmax) hmax = 2.5 * dmin;
+    if (2.5 * dmin < hmax) hmax = 2.5 * dmin;
     pn.hmax = hmax;
     double k0 = 0.0, h = pn.h0;
     int zoom = kZoom + 1;  // first panel [0, h0] split geometrically towards 0
@@ -203,7 +240,7 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
       for (int g = 0; g < kGL; ++g) {
         const double k = a0 + 0.5 * hh * (c_glx[g] + 1.0);
         const double w = 0.5 * hh * c_glw[g];
-        const double sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(k, 0.0)).re : 1.0;
+        const double sg = density(md, sc, c.lt, c.ls, c.a, c.b, cmk(k, 0.0)).re - c.sinf * exp(-k * c.zinf);
         const double base = w * exp(-k * z) * sg;
         const double j0v = (rho > 0.0) ? j0(k * rho) : 1.0;
         const double j1v = want1 ? j1(k * rho) : 0.0;
@@ -224,7 +261,7 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
     }
   } else {
     // imaginary axis: (2/pi) K_m(eta rho) (S eta)^n x {(-1)^{(n-m)/2} Re w, (-1)^{(n-m+1)/2} Im w},
-    // w = e^{-i eta z} sigma(i eta)
+    // w = e^{-i eta z} (sigma(i eta) - sinf e^{-i eta zinf})
     pn.kmax = (2.0 * nmax + 50.0) / rho;
     double hmax = 2.0 / rho;
     const double osc = z + c.zinf + 4.0 * max_thickness(md);
@@ -241,9 +278,12 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
       for (int g = 0; g < kGL; ++g) {
         const double et = a0 + 0.5 * hh * (c_glx[g] + 1.0);
         const double wq = 0.5 * hh * c_glw[g] * (2.0 / 3.14159265358979323846);
-        cplx sg = (md.L > 0) ? density(md, sc, c.lt, c.ls, c.a, c.b, cmk(0.0, et)) : cmk(1.0, 0.0);
-        double sn, cs;
+        cplx sg = density(md, sc, c.lt, c.ls, c.a, c.b, cmk(0.0, et));
+        double sn, cs, si, ci;
         sincos(et * z, &sn, &cs);
+        sincos(et * c.zinf, &si, &ci);
+        sg.re -= c.sinf * ci;
+        sg.im += c.sinf * si;
         const cplx wv = cmk(cs, -sn) * sg;
         double kk0, kk1;
         bessel_k01(et * rho, &kk0, &kk1);
@@ -275,15 +315,9 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
   double fn = 1.0;  // n!
   for (int n = 0; n <= nmax; ++n) {
     if (n > 0) fn *= n;
-    out0[n] = acc0[n] / fn;
-    if (out1 != nullptr) {
-      if (n >= 1 && rho > 0.0) {
-        // (n+1)! (n-1)! = n!^2 (n+1)/n
-        out1[n] = acc1[n] / (fn * sqrt((n + 1.0) / n));
-      } else {
-        out1[n] = 0.0;
-      }
-    }
+    out0[n] += acc0[n] / fn;
+    // (n+1)! (n-1)! = n!^2 (n+1)/n
+    if (want1 && n >= 1) out1[n] += acc1[n] / (fn * sqrt((n + 1.0) / n));
   }
 }
 
@@ -399,6 +433,30 @@ double zeta_inf(const Medium& md, int lt, int ls, int a, int b) {
   if (lt == ls) return (a == b) ? 0.0 : D(lt);
   if (lt < ls) return (b == 1 ? D(ls) : 0.0) + (md.d[lt] - md.d[ls - 1]) + (a == 2 ? D(lt) : 0.0);
   return (b == 2 ? D(ls) : 0.0) + (md.d[ls] - md.d[lt - 1]) + (a == 1 ? D(lt) : 0.0);
+}
+
+// Amplitude of the leading term of the density: the product of the local
+// reflection and transmission coefficients met along the shortest ray path of
+// zeta_inf (every other path crosses some finite layer twice more, so
+// sigma(k) e^{k zinf} - sinf = O(e^{-2 k dmin})).
+double sigma_inf(const Medium& md, int lt, int ls, int a, int b) {
+  if (md.L == 0) return 1.0;
+  auto rdn = [&](int i) { return (md.eps[i] - md.eps[i + 1]) / (md.eps[i] + md.eps[i + 1]); };
+  auto rup = [&](int i) { return (md.eps[i + 1] - md.eps[i]) / (md.eps[i] + md.eps[i + 1]); };
+  auto tdn = [&](int i) { return 2.0 * md.eps[i] / (md.eps[i] + md.eps[i + 1]); };
+  auto tup = [&](int i) { return 2.0 * md.eps[i + 1] / (md.eps[i] + md.eps[i + 1]); };
+  if (lt == ls) {
+    if (a == b) return (b == 1) ? rdn(ls) : rup(ls - 1);
+    return rdn(ls) * rup(ls - 1);
+  }
+  if (lt < ls) {
+    double s = (b == 2) ? 1.0 : rdn(ls);  // b = 1: down to d_ls and back up first
+    for (int i = ls - 1; i >= lt; --i) s *= tup(i);
+    return (a == 1) ? s : rup(lt - 1) * s;
+  }
+  double s = (b == 1) ? 1.0 : rup(ls - 1);
+  for (int i = ls + 1; i <= lt; ++i) s *= tdn(i - 1);
+  return (a == 2) ? s : rdn(lt) * s;
 }
 
 int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,

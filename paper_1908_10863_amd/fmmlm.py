@@ -40,13 +40,16 @@ class Stats(ctypes.Structure):
                 ("p2p_reaction_pairs", ctypes.c_int64), ("n_free_ops", ctypes.c_int64),
                 ("n_reaction_ops", ctypes.c_int64), ("n_sommerfeld_tasks", ctypes.c_int64),
                 ("root_side", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("tree_seconds", ctypes.c_double), ("lists_seconds", ctypes.c_double),
+                ("ops_seconds", ctypes.c_double), ("table_seconds", ctypes.c_double),
+                ("nearfield_seconds", ctypes.c_double)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
            "fmm_layered_strerror", "fmm_layered_plan_stats", "fmm_layered_plan_tree",
            "fmm_layered_sommerfeld", "fmm_layered_density", "fmm_layered_profile_begin",
-           "fmm_layered_profile_end"]
+           "fmm_layered_profile_end", "fmm_layered_density_asymptotic"]
 STAGES = ["gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "p2p_reaction", "combine"]
 
 _lib = None
@@ -59,6 +62,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    # torch brings its own HIP runtime: load it first so that the library and
+    # torch share one runtime (and one device context) in this process
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
@@ -88,6 +94,10 @@ def lib():
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp, vp,
                                       vp, vp]
     L.fmm_layered_density.restype = ctypes.c_int
+    L.fmm_layered_density_asymptotic.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                  dp, dp]
+    L.fmm_layered_density_asymptotic.restype = ctypes.c_int
     L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
     L.fmm_layered_profile_begin.restype = ctypes.c_int
     L.fmm_layered_profile_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -222,3 +232,14 @@ def density(d, eps, lt, ls, a, b, k, stream=None):
     check(lib().fmm_layered_density(len(d), _ptr(d), _ptr(eps), lt, ls, a, b, len(k), _ptr(kr),
                                     _ptr(ki), _ptr(orr), _ptr(oi), _stream_handle(stream)))
     return orr + 1j * oi
+
+
+def density_asymptotic(d, eps, lt, ls, a, b):
+    """(sinf, zinf): sigma^{ab}_{lt,ls}(k) ~ sinf e^{-k zinf} as k -> infinity (host call)."""
+    d = _host(d, np.float64)
+    eps = _host(eps, np.float64)
+    si = ctypes.c_double()
+    zi = ctypes.c_double()
+    check(lib().fmm_layered_density_asymptotic(len(d), _ptr(d), _ptr(eps), lt, ls, a, b,
+                                               ctypes.byref(si), ctypes.byref(zi)))
+    return si.value, zi.value
