@@ -26,6 +26,8 @@ Contents and the passage each follows:
                         eq. scaledsommerfeldint, any number of layers.
 * ``morton_sort``      the octree's key definition and stable sort.
 * ``polarization_z``   equivalent polarization source heights (eq. eqpolarizedsource).
+* ``mlp``              (submodule) the surrogate network of the learned form:
+                        forward pass, loss, chain-rule gradient, Adam step.
 
 Pins for every function are in tests/test_oracle_*.py.
 """
