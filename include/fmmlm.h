@@ -57,6 +57,7 @@ extern "C" {
 #define FMMLM_REACTION 2u        /* parts bit: reaction components */
 
 typedef struct fmmlm_plan_s* fmmlm_plan_t;
+typedef struct fmmlm_surrogate_s* fmmlm_surrogate_t;
 
 typedef struct {
   int32_t leaf_cap;        /* a box is split while it holds more points (default 64) */
@@ -73,6 +74,11 @@ typedef struct {
                               (and not adjacent); 4 is the classic one-box separation.
                               Range 4..12, default 6 */
   int32_t reserved[3];     /* must be 0 */
+  fmmlm_surrogate_t surrogate; /* learned form (default NULL = quadrature): a trained network
+                              for this medium serves the reaction Sommerfeld initial values
+                              and near-field kernels inside its domain, the quadrature the
+                              rest (see fmm_layered_surrogate_train).  The plan does not
+                              keep the handle after it returns */
 } fmmlm_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -159,6 +165,12 @@ typedef struct {
   double ops_seconds;          /*   M2L operators (free and reaction, incl. table_seconds) */
   double table_seconds;        /*   Sommerfeld initial values + recurrence of the reaction M2L */
   double nearfield_seconds;    /*   reaction near-field kernel values */
+  int64_t surrogate_tasks;     /* learned form: Sommerfeld tasks served by the network ... */
+  int64_t surrogate_pairs;     /*   ... and near-field pairs (the rest took the quadrature) */
+  double surrogate_check;      /*   learned form against the quadrature on up to 256 sampled
+                                    tasks: the largest R1 max_{N,M} 0.87^N |difference of
+                                    S^N I_{N,M}|, R1 = |(rho, z + zinf)| (the error relative to
+                                    the interaction 1/R1 that the operator carries) */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
@@ -196,6 +208,109 @@ int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, con
                            int32_t lt, int32_t ls, int32_t a, int32_t b, double S, int64_t npts,
                            const double* rho, const double* z, int32_t nmax, double* out,
                            void* hip_stream);
+
+/* ---- learned form: image ladder + MLP surrogate of the reaction Sommerfeld integrals
+ *
+ * Reaction component (lt, ls, a, b) of the medium, density sigma(k) with
+ * leading term sinf e^{-k zinf} (eq. densityasymptotic).  The 4p+1 initial
+ * values S^n I_{n,0}, S^n I_{n,1} of eq. scaledsommerfeldint (p = the
+ * surrogate's order) are served as the sum of three parts:
+ *   1. the leading term, integrated in closed form (an image at zeta + zinf);
+ *   2. a ladder of kLadder = 8 rungs c_j e^{-k (zinf + j delta)}, delta = 2 dmin
+ *      (dmin the thinnest finite layer), also closed-form images; c_j is a
+ *      weighted least-squares fit of sigma(k) e^{k zinf} - sinf, made once per
+ *      component when the surrogate is created (densities from the GPU);
+ *   3. the network (4 layers of width 128, tanh, FP32): output j, times
+ *      yscale S^n / (0.7^n R2^{n+1}), R2 = |(rho, zeta + zinf + 2 dmin)|, is
+ *      what parts 1 and 2 leave (degree n_j, order m_j: outputs 0..2p are
+ *      (n, 0), outputs 2p+1..4p are (n - 2p, 1)).
+ * Orders M >= 2 follow by eq. recurrence in FP64, as without the network.
+ * Outside the trained (rho, zeta) box the quadrature is used (fallback); the
+ * quadrature also judges the learned form: plans report the largest
+ * deviation on sampled tasks (fmmlm_stats.surrogate_check).
+ * Network inputs: the component (one-hot) and
+ * (2 rho/rho_max - 1, 2 zeta/zeta_max - 1, 2 Z2/R2 - 1, 4 dmin/R2 - 1).
+ * Components are numbered over the medium's 2L sides (layer, side) in order
+ * (layer 0 side 1, layer 1 side 1, layer 1 side 2, ...): c = t * 2L + s for
+ * target side t and source side s.  Needs at least two interfaces (with one,
+ * the density is its leading term and the quadrature is not used at all).
+ */
+typedef struct {
+  int64_t nsamples;        /* samples generated by the quadrature (default 2097152);
+                              1/32 of them are held out for validation */
+  int32_t steps;           /* Adam steps (default 6000) */
+  int32_t batch;           /* minibatch, a multiple of 64 (default 8192) */
+  double lr;               /* peak learning rate (default 2e-3): 2% linear warm-up,
+                              then cosine decay to lr/100 */
+  uint64_t seed;           /* initialisation, samples, minibatches (default 1) */
+  int32_t reserved[4];     /* must be 0 */
+} fmmlm_train_opts;
+
+typedef struct {
+  int64_t n_train, n_val, n_params;
+  int32_t n_components, n_outputs;
+  double sample_seconds;   /* generating the samples (quadrature on the GPU) */
+  double train_seconds;    /* the Adam steps */
+  double loss_first;       /* mean minibatch loss over the first and ...             */
+  double loss_last;        /* ... last 2% of the steps (normalised outputs y)        */
+  double val_rms, val_max; /* held-out error of y (network output units)             */
+  double yscale;           /* the output unit: rms of the targets in physical units  */
+  double ladder_fit;       /* largest relative weighted residual of the ladder fits  */
+} fmmlm_train_report;
+
+void fmmlm_default_train_opts(fmmlm_train_opts* opts);
+
+/*
+ * A new, untrained network (Glorot-uniform weights from seed) for the medium
+ * (host arrays as in fmm_layered_plan), order p (outputs 4p+1) and the
+ * (rho, zeta) box [0, rho_max] x (0, zeta_max].  Errors: FMMLM_EINVAL
+ * (p out of range, non-positive box), FMMLM_EUNSUPPORTED (fewer than two
+ * interfaces), medium errors, FMMLM_EDEVICE.
+ */
+int fmm_layered_surrogate_create(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                                 int32_t p, double rho_max, double zeta_max, uint64_t seed,
+                                 fmmlm_surrogate_t* out);
+
+/* The same for a plan's medium and p, with the box covering every (rho, zeta)
+ * the plan's trees can produce: rho_max = sqrt(2) W, zeta_max = 2 W, W the
+ * common root box side. */
+int fmm_layered_surrogate_create_for_plan(fmmlm_plan_t plan, uint64_t seed, fmmlm_surrogate_t* out);
+
+/* Generates opts->nsamples samples with the quadrature and trains the network
+ * in place with its own forward/backward/Adam kernels on hip_stream
+ * (synchronised on return).  opts NULL = defaults; rep may be NULL. */
+int fmm_layered_surrogate_train(fmmlm_surrogate_t s, const fmmlm_train_opts* opts, void* hip_stream,
+                                fmmlm_train_report* rep);
+
+int fmm_layered_surrogate_destroy(fmmlm_surrogate_t s);
+
+/* Parameters as one host float vector (layout in the network description
+ * above: E [ncomp][128], A [4][128], b1, W2 [128][128], b2, W3, b3, W4 [128][nout],
+ * b4, W[k][j] mapping input k to output j).  *n receives the count; get or set
+ * may be NULL (get copies out, then set copies in). */
+int fmm_layered_surrogate_params(fmmlm_surrogate_t s, float* get, const float* set, int64_t* n);
+
+/* One forward and backward pass on the GPU over n samples (host arrays:
+ * comp [n] component index, feat [n][4] features, target [n][nout]): the
+ * mean squared error into *loss and its gradient into grad [nparams] (host).
+ * For checking the training kernels. */
+int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
+                               const float* target, double* loss, float* grad, void* hip_stream);
+
+/* The training samples fmm_layered_surrogate_train draws for seed: n samples
+ * into host arrays comp [n], rho [n], zeta [n], feat [n][4], target [n][nout]
+ * (target = what the leading term and the ladder leave of the quadrature's
+ * initial values, times 0.7^n R2^{n+1} / yscale: the network's output units). */
+int fmm_layered_surrogate_samples(fmmlm_surrogate_t s, int64_t n, uint64_t seed, int32_t* comp, double* rho,
+                                  double* zeta, float* feat, float* target, void* hip_stream);
+
+/* S^N I_{N,M}(rho, z) for 0 <= M <= N <= nmax (nmax <= 2p of the surrogate)
+ * through the learned form, with the same layout as fmm_layered_sommerfeld; used[i]
+ * (may be NULL) is 1 where the network served point i, 0 where the quadrature
+ * did.  Host arrays. */
+int fmm_layered_surrogate_eval(fmmlm_surrogate_t s, int32_t lt, int32_t ls, int32_t a, int32_t b, double S,
+                               int64_t npts, const double* rho, const double* z, int32_t nmax, double* out,
+                               int32_t* used, void* hip_stream);
 
 /*
  * Leading term of a reaction density as k -> infinity (eq. densityasymptotic):

@@ -289,6 +289,56 @@ void free_plan(fmmlm_plan_s* P) {
   delete P;
 }
 
+// The quadrature judges the learned form: up to 256 tasks spread over the
+// list are recomputed without it.  A task's error is R1 max_{N,M} 0.87^N
+// |S^N I_{N,M} (learned) - S^N I_{N,M} (quadrature)|, R1 = |(rho, z + zinf)|:
+// relative to the interaction 1/R1 that the task's operator carries, with the
+// weight (0.87)^N that the scaled expansions of two boxes (radius at most
+// 0.87 S) put on degree N.  The largest goes to the plan's stats.
+int surrogate_check(fmmlm_plan_s* P, const std::vector<CompInfo>& comps, const std::vector<SommTask>& tasks,
+                    const double* d_tables, hipStream_t st) {
+  const int64_t nt = (int64_t)tasks.size();
+  const int64_t k = std::min<int64_t>(nt, 256);
+  if (k == 0) return FMMLM_OK;
+  std::vector<SommTask> pick(k);
+  std::vector<int64_t> idx(k);
+  for (int64_t i = 0; i < k; ++i) {
+    idx[i] = i * nt / k;
+    pick[i] = tasks[idx[i]];
+  }
+  const size_t per = (size_t)P->ng;
+  const int nmax = 2 * P->p;
+  double* dq = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dq, k * per * sizeof(double)));
+  int rc = gpu_sommerfeld_tables(P->medium, comps, pick, nmax, dq, st);
+  std::vector<double> q(k * per), g(k * per);
+  if (rc == FMMLM_OK) {
+    hipError_t e = hipMemcpy(q.data(), dq, k * per * sizeof(double), hipMemcpyDeviceToHost);
+    for (int64_t i = 0; i < k && e == hipSuccess; ++i)
+      e = hipMemcpy(g.data() + i * per, d_tables + idx[i] * per, per * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(dq);
+  if (rc) return rc;
+  double worst = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    const SommTask& tk = pick[i];
+    const double Z1 = tk.z + comps[tk.comp].zinf;
+    const double R1 = std::sqrt(tk.rho * tk.rho + Z1 * Z1);
+    double w = R1;
+    for (int n = 0; n <= nmax; ++n, w *= 0.87)
+      for (int m = 0; m <= n; ++m) {
+        const size_t j = (size_t)n * (n + 1) / 2 + m;
+        worst = std::max(worst, w * std::fabs(q[i * per + j] - g[i * per + j]));
+      }
+  }
+  P->stats.surrogate_check = worst;
+  return FMMLM_OK;
+}
+
 int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<double>& Y,
                const std::vector<double>& Z, const std::vector<int32_t>& LAY, hipStream_t st) {
   const int L = P->L;
@@ -494,6 +544,16 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       comps.push_back(make_comp(P->medium, P->trees[t].layer, P->trees[s].layer, P->trees[t].side,
                                 P->trees[s].side));
     }
+  const fmmlm_surrogate_s* sur = P->opts.surrogate;
+  std::vector<int32_t> smap;  // plan component -> surrogate component
+  if (sur) {
+    for (int t = 0; t < nt; ++t)
+      for (int s = 0; s < nt; ++s) {
+        const TreeInfo& A = P->trees[t];
+        const TreeInfo& S = P->trees[s];
+        smap.push_back(side_index(L, A.layer, A.side) * 2 * L + side_index(L, S.layer, S.side));
+      }
+  }
   for (int t = 0; t < nt; ++t)
     for (int s = 0; s < nt; ++s) B.process_reac(B.root[t], B.root[s], t * nt + s);
   // ---- leaves
@@ -718,8 +778,14 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (!B.tasks.empty()) {
     FMM_HIP_TRY(hipMalloc(&tables, B.tasks.size() * (size_t)P->ng * sizeof(double)));
     const auto ts = std::chrono::steady_clock::now();
-    rc = gpu_sommerfeld_tables(P->medium, comps, B.tasks, 2 * p, tables, st);
+    if (sur) {
+      rc = gpu_surrogate_tables(P->medium, comps, smap, sur->d_lad, sur->dm, B.tasks, 2 * p, sur->net, tables,
+                                &P->stats.surrogate_tasks, st, nullptr);
+    } else {
+      rc = gpu_sommerfeld_tables(P->medium, comps, B.tasks, 2 * p, tables, st);
+    }
     P->stats.table_seconds = seconds_since(ts);
+    if (rc == FMMLM_OK && sur) rc = surrogate_check(P, comps, B.tasks, tables, st);
     if (rc) {
       hipFree(tables);
       return rc;
@@ -757,7 +823,14 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     FMM_HIP_TRY(hipMemcpyAsync(ds, rp_s.data(), npairs * 4, hipMemcpyHostToDevice, st));
     FMM_HIP_TRY(hipMemcpyAsync(dc, rp_c.data(), npairs * 4, hipMemcpyHostToDevice, st));
     const auto ts = std::chrono::steady_clock::now();
-    rc = gpu_reaction_nearfield(P->medium, comps, dt, ds, dc, npairs, P->px, P->py, P->ph, P->rp_val, st);
+    if (sur) {
+      int64_t nfb = 0;
+      rc = gpu_surrogate_nearfield(P->medium, comps, smap, sur->d_lad, sur->dm, dt, ds, dc, npairs, P->px,
+                                   P->py, P->ph, sur->net, P->rp_val, &nfb, st);
+      P->stats.surrogate_pairs = npairs - nfb;
+    } else {
+      rc = gpu_reaction_nearfield(P->medium, comps, dt, ds, dc, npairs, P->px, P->py, P->ph, P->rp_val, st);
+    }
     P->stats.nearfield_seconds = seconds_since(ts);
     hipFree(dt);
     hipFree(ds);
@@ -786,6 +859,138 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     if ((rc = dev_upload(P, &P->bbox, bb, st))) return rc;
   }
   FMM_HIP_TRY(hipStreamSynchronize(st));
+  return FMMLM_OK;
+}
+
+// Least squares min ||A x - b||_2 for a dense m x n matrix (row-major, m >= n)
+// by Householder QR on unit-norm columns; x [n].  Returns false if a column
+// is zero or the factor is singular.
+bool lstsq_qr(std::vector<double> A, std::vector<double> b, int m, int n, std::vector<double>& x) {
+  std::vector<double> cs(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double ss = 0.0;
+    for (int i = 0; i < m; ++i) ss += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+    if (!(ss > 0.0)) return false;
+    cs[j] = 1.0 / std::sqrt(ss);
+    for (int i = 0; i < m; ++i) A[(size_t)i * n + j] *= cs[j];
+  }
+  for (int j = 0; j < n; ++j) {
+    double nrm = 0.0;
+    for (int i = j; i < m; ++i) nrm += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0)) return false;
+    const double alpha = A[(size_t)j * n + j] > 0.0 ? -nrm : nrm;
+    std::vector<double> v(m - j);
+    for (int i = j; i < m; ++i) v[i - j] = A[(size_t)i * n + j];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double t : v) vv += t * t;
+    if (vv > 0.0) {
+      for (int c = j; c < n; ++c) {
+        double dot = 0.0;
+        for (int i = j; i < m; ++i) dot += v[i - j] * A[(size_t)i * n + c];
+        const double f = 2.0 * dot / vv;
+        for (int i = j; i < m; ++i) A[(size_t)i * n + c] -= f * v[i - j];
+      }
+      double dot = 0.0;
+      for (int i = j; i < m; ++i) dot += v[i - j] * b[i];
+      const double f = 2.0 * dot / vv;
+      for (int i = j; i < m; ++i) b[i] -= f * v[i - j];
+    }
+  }
+  x.assign(n, 0.0);
+  for (int j = n - 1; j >= 0; --j) {
+    double t = b[j];
+    for (int c = j + 1; c < n; ++c) t -= A[(size_t)j * n + c] * x[c];
+    const double r = A[(size_t)j * n + j];
+    if (!(std::fabs(r) > 0.0)) return false;
+    x[j] = t / r;
+  }
+  for (int j = 0; j < n; ++j) x[j] *= cs[j];
+  return true;
+}
+
+// Ladder of each surrogate component: sigma(k) e^{k zinf} - sinf ~ sum_j c_j
+// t^j, t = e^{-k delta}, j = 1..kLadder, fitted in least squares with the
+// weight e^{-k zmin} (zmin = dmin / 10, the smallest height sum the fit is
+// tuned for) on 200 uniform nodes in [0, 2.5 / dmin] and 300 geometric nodes
+// up to kmax = min(500 / dmin, 600 / zinf).  The densities come from the GPU
+// (the plan's own recursion); the fit runs once per surrogate on the host.
+int fit_ladders(fmmlm_surrogate_s* S, hipStream_t st) {
+  const double dmin = S->dm.dmin, delta = S->dm.delta, zmin = 0.1 * dmin;
+  const int nlin = 200, ngeo = 300, m = nlin + ngeo;
+  const size_t nc = S->comps.size();
+  S->lad.assign(nc * kLadder, 0.0);
+  S->ladder_fit = 0.0;
+  std::vector<double> kre(m), kim(m, 0.0), ore(m), oim(m), A((size_t)m * kLadder), b(m), x;
+  for (size_t c = 0; c < nc; ++c) {
+    const CompInfo& ci = S->comps[c];
+    double kmax = 500.0 / dmin;
+    if (ci.zinf > 0.0) kmax = std::min(kmax, 600.0 / ci.zinf);
+    const double k1 = std::min(2.5 / dmin, 0.5 * kmax);
+    for (int i = 0; i < nlin; ++i) kre[i] = k1 * i / nlin;
+    for (int i = 0; i < ngeo; ++i) kre[nlin + i] = k1 * std::pow(kmax / k1, (double)i / (ngeo - 1));
+    int rc = gpu_density(S->medium, ci, m, kre.data(), kim.data(), ore.data(), oim.data(), st);
+    if (rc) return rc;
+    double gn = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double k = kre[i], w = std::exp(-k * zmin), t = std::exp(-k * delta);
+      b[i] = w * (ore[i] * std::exp(k * ci.zinf) - ci.sinf);
+      gn += b[i] * b[i];
+      double tj = t;
+      for (int j = 0; j < kLadder; ++j, tj *= t) A[(size_t)i * kLadder + j] = w * tj;
+    }
+    if (!(gn > 0.0)) continue;  // remainder identically zero: no rungs
+    if (!lstsq_qr(A, b, m, kLadder, x)) {
+      set_last_error("the ladder fit of a reaction density failed");
+      return FMMLM_EUNSUPPORTED;
+    }
+    double rn = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double f = 0.0;
+      for (int j = 0; j < kLadder; ++j) f += A[(size_t)i * kLadder + j] * x[j];
+      rn += (f - b[i]) * (f - b[i]);
+    }
+    S->ladder_fit = std::max(S->ladder_fit, std::sqrt(rn / gn));
+    std::copy(x.begin(), x.end(), S->lad.begin() + c * kLadder);
+  }
+  FMM_HIP_TRY(hipMalloc(&S->d_lad, S->lad.size() * sizeof(double)));
+  FMM_HIP_TRY(hipMemcpy(S->d_lad, S->lad.data(), S->lad.size() * sizeof(double), hipMemcpyHostToDevice));
+  return FMMLM_OK;
+}
+
+// Output unit of the network: the rms of the targets over a pilot sample.
+int pilot_yscale(fmmlm_surrogate_s* S, uint64_t seed, hipStream_t st) {
+  constexpr int64_t kPilot = 32768;
+  const int nout = 2 * S->nmax + 1;
+  int32_t* dc = nullptr;
+  float *df = nullptr, *dy = nullptr;
+  S->dm.yscale = 1.0;
+  int rc = FMMLM_OK;
+  hipError_t e = hipMalloc(&dc, kPilot * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&df, kPilot * 4 * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&dy, (size_t)kPilot * nout * sizeof(float));
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  std::vector<float> y((size_t)kPilot * nout);
+  if (rc == FMMLM_OK)
+    rc = gpu_surrogate_samples(S->medium, S->comps, S->d_lad, S->dm, S->nmax, seed ^ 0x51CA1Eull, kPilot, dc, df,
+                               dy, st);
+  if (rc == FMMLM_OK && (e = hipMemcpy(y.data(), dy, y.size() * sizeof(float), hipMemcpyDeviceToHost)) !=
+                            hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  hipFree(dc);
+  hipFree(df);
+  hipFree(dy);
+  if (rc) return rc;
+  double ss = 0.0;
+  for (float v : y) ss += (double)v * v;
+  const double rms = std::sqrt(ss / y.size());
+  if (rms > 0.0 && std::isfinite(rms)) S->dm.yscale = rms;
   return FMMLM_OK;
 }
 
@@ -826,12 +1031,21 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
     if (o.reserved[i] != 0) return FMMLM_EINVAL;
   if (o.fp64_top_levels < 0 || o.fp64_top_levels > kMaxLevel + 1) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (o.surrogate) {
+    // the network must describe this medium and cover orders up to 2p
+    const fmmlm_surrogate_s* S = o.surrogate;
+    if (S->L != n_interfaces || S->p < p) return FMMLM_EINVAL;
+  }
   std::vector<double> dv, ev, X, Y, Z;
   std::vector<int32_t> LAY;
   int rc;
   if ((rc = fetch(z_interfaces, n_interfaces, dv))) return rc;
   if ((rc = fetch(eps, n_interfaces + 1, ev))) return rc;
   if ((rc = validate_medium(n_interfaces, dv, ev))) return rc;
+  if (o.surrogate && (o.surrogate->d != dv || o.surrogate->eps != ev)) {
+    set_last_error("the surrogate was trained for another medium");
+    return FMMLM_EINVAL;
+  }
   if ((rc = fetch(x, n, X)) || (rc = fetch(y, n, Y)) || (rc = fetch(z, n, Z)) || (rc = fetch(layer_id, n, LAY)))
     return rc;
   const int L = n_interfaces;
@@ -867,6 +1081,7 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
     free_plan(P);
     return rc;
   }
+  P->opts.surrogate = nullptr;  // not kept past planning
   P->stats.n_points = n;
   P->stats.n_tree_points = P->NP;
   P->stats.n_trees = (int32_t)P->trees.size();
@@ -1054,6 +1269,280 @@ int fmm_layered_profile_end(fmmlm_plan_t plan, double* stage_ms, int64_t* n_eval
   plan->prof_ev.clear();
   plan->prof_cap = plan->prof_used = 0;
   return FMMLM_OK;
+}
+
+// ---- learned form ---------------------------------------------------------
+void fmmlm_default_train_opts(fmmlm_train_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nsamples = (int64_t)1 << 21;
+  o->steps = 6000;
+  o->batch = 8192;
+  o->lr = 2e-3;
+  o->seed = 1;
+}
+
+int fmm_layered_surrogate_create(int32_t n_interfaces, const double* z_interfaces, const double* eps, int32_t p,
+                                 double rho_max, double zeta_max, uint64_t seed, fmmlm_surrogate_t* out) {
+  if (!out) return FMMLM_EINVAL;
+  *out = nullptr;
+  if (!z_interfaces || !eps || p < 1 || p > FMMLM_PMAX) return FMMLM_EINVAL;
+  if (!(rho_max > 0.0) || !(zeta_max > 0.0) || !std::isfinite(rho_max) || !std::isfinite(zeta_max))
+    return FMMLM_EINVAL;
+  if (n_interfaces < 1 || n_interfaces > kMaxL) return FMMLM_EINVAL;
+  std::vector<double> dv, ev;
+  int rc;
+  if ((rc = fetch(z_interfaces, n_interfaces, dv))) return rc;
+  if ((rc = fetch(eps, n_interfaces + 1, ev))) return rc;
+  if ((rc = validate_medium(n_interfaces, dv, ev))) return rc;
+  if (n_interfaces < 2) {
+    set_last_error("the learned form needs at least two interfaces");
+    return FMMLM_EUNSUPPORTED;
+  }
+  fmmlm_surrogate_s* S = new (std::nothrow) fmmlm_surrogate_s();
+  if (!S) return FMMLM_ENOMEM;
+  const int L = n_interfaces;
+  S->L = L;
+  S->d = dv;
+  S->eps = ev;
+  S->medium = make_medium(L, dv.data(), ev.data());
+  S->p = p;
+  S->nmax = 2 * p;
+  double dmin = 0.0;
+  for (int i = 1; i < L; ++i) {
+    const double t = dv[i - 1] - dv[i];
+    if (dmin == 0.0 || t < dmin) dmin = t;
+  }
+  S->dm = SurrogateDomain{rho_max, zeta_max, dmin, 2.0 * dmin, 1.0};
+  std::vector<std::pair<int, int>> sides;
+  for (int l = 0; l <= L; ++l)
+    for (int side = 1; side <= 2; ++side) {
+      if ((side == 1 && l > L - 1) || (side == 2 && l < 1)) continue;
+      sides.push_back({l, side});
+    }
+  for (auto& t : sides)
+    for (auto& u : sides) S->comps.push_back(make_comp(S->medium, t.first, u.first, t.second, u.second));
+  S->net.ncomp = (int)S->comps.size();
+  S->net.nout = 2 * S->nmax + 1;
+  mlp_layout(S->net);
+  (void)hipGetDevice(&S->device);
+  hipStream_t st = nullptr;
+  hipError_t e = hipMalloc(&S->net.params, S->net.nparams * sizeof(float));
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  if (rc == FMMLM_OK) rc = fit_ladders(S, st);
+  if (rc == FMMLM_OK) rc = pilot_yscale(S, seed, st);
+  if (rc == FMMLM_OK) rc = gpu_mlp_init(S->net, seed, st);
+  if (rc == FMMLM_OK && hipDeviceSynchronize() != hipSuccess) rc = FMMLM_EDEVICE;
+  if (rc) {
+    hipFree(S->net.params);
+    hipFree(S->d_lad);
+    delete S;
+    return rc;
+  }
+  *out = S;
+  return FMMLM_OK;
+}
+
+int fmm_layered_surrogate_create_for_plan(fmmlm_plan_t plan, uint64_t seed, fmmlm_surrogate_t* out) {
+  if (!plan || !out) return FMMLM_EINVAL;
+  return fmm_layered_surrogate_create(plan->L, plan->d.data(), plan->eps.data(), plan->p, std::sqrt(2.0) * plan->W,
+                                      2.0 * plan->W, seed, out);
+}
+
+int fmm_layered_surrogate_destroy(fmmlm_surrogate_t s) {
+  if (!s) return FMMLM_EINVAL;
+  hipFree(s->net.params);
+  hipFree(s->d_lad);
+  delete s;
+  return FMMLM_OK;
+}
+
+int fmm_layered_surrogate_train(fmmlm_surrogate_t s, const fmmlm_train_opts* opts, void* hip_stream,
+                                fmmlm_train_report* rep) {
+  if (!s) return FMMLM_EINVAL;
+  fmmlm_train_opts o;
+  fmmlm_default_train_opts(&o);
+  if (opts) o = *opts;
+  for (int i = 0; i < 4; ++i)
+    if (o.reserved[i] != 0) return FMMLM_EINVAL;
+  if (o.nsamples < 128 || o.nsamples > ((int64_t)1 << 28) || o.steps < 0 || o.batch < 64 || o.batch % 64 ||
+      o.batch > (1 << 20) || !(o.lr > 0.0))
+    return FMMLM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t n = o.nsamples, nval = n / 32, ntrain = n - nval;
+  const int nout = s->net.nout;
+  int32_t* comp = nullptr;
+  float *feat = nullptr, *y = nullptr, *vout = nullptr;
+  auto cleanup = [&]() {
+    hipFree(comp);
+    hipFree(feat);
+    hipFree(y);
+    hipFree(vout);
+  };
+  FMM_HIP_TRY(hipMalloc(&comp, n * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&feat, n * 4 * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&y, (size_t)n * nout * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&vout, (size_t)std::max<int64_t>(nval, 1) * nout * sizeof(float)));
+  fmmlm_train_report r;
+  std::memset(&r, 0, sizeof(r));
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = gpu_surrogate_samples(s->medium, s->comps, s->d_lad, s->dm, s->nmax, o.seed, n, comp, feat, y, st);
+  r.sample_seconds = seconds_since(t0);
+  if (rc == FMMLM_OK) {
+    t0 = std::chrono::steady_clock::now();
+    rc = gpu_mlp_train(s->net, comp, feat, y, ntrain, o.steps, o.batch, o.lr, o.seed, &r.loss_first,
+                       &r.loss_last, st);
+    r.train_seconds = seconds_since(t0);
+  }
+  if (rc == FMMLM_OK && nval > 0) {
+    rc = gpu_mlp_forward(s->net, comp + ntrain, feat + ntrain * 4, nval, vout, nout, nout, nullptr, nullptr,
+                         nullptr, st);
+    std::vector<float> a((size_t)nval * nout), b((size_t)nval * nout);
+    if (rc == FMMLM_OK) {
+      hipError_t e = hipMemcpyAsync(a.data(), vout, a.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b.data(), y + ntrain * nout, b.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        set_last_error(hipGetErrorString(e));
+        rc = FMMLM_EDEVICE;
+      }
+    }
+    double ss = 0.0, mx = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+      const double dd = (double)a[i] - (double)b[i];
+      ss += dd * dd;
+      mx = std::max(mx, std::fabs(dd));
+    }
+    r.val_rms = std::sqrt(ss / std::max<size_t>(a.size(), 1));
+    r.val_max = mx;
+  }
+  cleanup();
+  r.n_train = ntrain;
+  r.n_val = nval;
+  r.n_params = s->net.nparams;
+  r.n_components = s->net.ncomp;
+  r.n_outputs = nout;
+  r.yscale = s->dm.yscale;
+  r.ladder_fit = s->ladder_fit;
+  if (rep) *rep = r;
+  return rc;
+}
+
+int fmm_layered_surrogate_params(fmmlm_surrogate_t s, float* get, const float* set, int64_t* n) {
+  if (!s) return FMMLM_EINVAL;
+  if (n) *n = s->net.nparams;
+  if (get) FMM_HIP_TRY(hipMemcpy(get, s->net.params, s->net.nparams * sizeof(float), hipMemcpyDeviceToHost));
+  if (set) FMM_HIP_TRY(hipMemcpy(s->net.params, set, s->net.nparams * sizeof(float), hipMemcpyHostToDevice));
+  return FMMLM_OK;
+}
+
+int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
+                               const float* target, double* loss, float* grad, void* hip_stream) {
+  if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !feat || !target || !loss || !grad) return FMMLM_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (comp[i] < 0 || comp[i] >= s->net.ncomp) return FMMLM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nout = s->net.nout;
+  int32_t* dc = nullptr;
+  float *df = nullptr, *dy = nullptr, *dg = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, n * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&df, n * 4 * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dy, (size_t)n * nout * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dg, s->net.nparams * sizeof(float)));
+  int rc = FMMLM_OK;
+  hipError_t e = hipMemcpy(dc, comp, n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(df, feat, n * 4 * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dy, target, (size_t)n * nout * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  if (rc == FMMLM_OK) rc = gpu_mlp_grad(s->net, dc, df, dy, n, dg, loss, st);
+  if (rc == FMMLM_OK) {
+    e = hipMemcpy(grad, dg, s->net.nparams * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(dc);
+  hipFree(df);
+  hipFree(dy);
+  hipFree(dg);
+  return rc;
+}
+
+int fmm_layered_surrogate_samples(fmmlm_surrogate_t s, int64_t n, uint64_t seed, int32_t* comp, double* rho,
+                                  double* zeta, float* feat, float* target, void* hip_stream) {
+  if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !rho || !zeta || !feat || !target) return FMMLM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nout = s->net.nout;
+  int32_t* dc = nullptr;
+  float *df = nullptr, *dy = nullptr;
+  double* drz = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, n * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&df, n * 4 * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dy, (size_t)n * nout * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&drz, n * 2 * sizeof(double)));
+  int rc = gpu_surrogate_samples(s->medium, s->comps, s->d_lad, s->dm, s->nmax, seed, n, dc, df, dy, st, drz);
+  std::vector<double> rz(2 * n);
+  if (rc == FMMLM_OK) {
+    hipError_t e = hipMemcpy(comp, dc, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(feat, df, n * 4 * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(target, dy, (size_t)n * nout * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(rz.data(), drz, n * 2 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      rho[i] = rz[2 * i];
+      zeta[i] = rz[2 * i + 1];
+    }
+  }
+  hipFree(dc);
+  hipFree(df);
+  hipFree(dy);
+  hipFree(drz);
+  return rc;
+}
+
+int fmm_layered_surrogate_eval(fmmlm_surrogate_t s, int32_t lt, int32_t ls, int32_t a, int32_t b, double S,
+                               int64_t npts, const double* rho, const double* z, int32_t nmax, double* out,
+                               int32_t* used, void* hip_stream) {
+  if (!s || npts < 1 || npts > ((int64_t)1 << 28) || !rho || !z || !out || nmax < 0 || nmax > s->nmax ||
+      !(S > 0.0))
+    return FMMLM_EINVAL;
+  const int L = s->L;
+  if (lt < 0 || lt > L || ls < 0 || ls > L || a < 1 || a > 2 || b < 1 || b > 2) return FMMLM_EINVAL;
+  if ((a == 1 && lt > L - 1) || (a == 2 && lt < 1) || (b == 1 && ls > L - 1) || (b == 2 && ls < 1))
+    return FMMLM_EINVAL;
+  std::vector<CompInfo> comps{make_comp(s->medium, lt, ls, a, b)};
+  std::vector<int32_t> smap{side_index(L, lt, a) * 2 * L + side_index(L, ls, b)};
+  std::vector<SommTask> tasks(npts);
+  for (int64_t i = 0; i < npts; ++i) {
+    if (!(rho[i] >= 0.0) || !(z[i] > 0.0)) return FMMLM_EINVAL;
+    tasks[i] = SommTask{0, S, rho[i], z[i]};
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double* d = nullptr;
+  const size_t per = ncoef(nmax);
+  FMM_HIP_TRY(hipMalloc(&d, npts * per * sizeof(double)));
+  int64_t nu = 0;
+  int rc = gpu_surrogate_tables(s->medium, comps, smap, s->d_lad, s->dm, tasks, nmax, s->net, d, &nu, st, used);
+  if (rc == FMMLM_OK) {
+    hipError_t e = hipMemcpy(out, d, npts * per * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(d);
+  return rc;
 }
 
 }  // extern "C"

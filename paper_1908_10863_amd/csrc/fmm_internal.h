@@ -189,6 +189,46 @@ inline CompInfo make_comp(const Medium& md, int lt, int ls, int a, int b) {
   return CompInfo{lt, ls, a, b, zeta_inf(md, lt, ls, a, b), sigma_inf(md, lt, ls, a, b)};
 }
 
+// learned form: image ladder + network, and the trained domain
+struct SurrogateDomain {
+  double rho_max, zeta_max;  // trained (rho, zeta) box; outside it the quadrature is used
+  double dmin;               // thinnest finite layer (the remainder's decay length offset)
+  double delta;              // ladder spacing 2 dmin: rung j sits at zeta + zinf + j delta
+  double yscale;             // network output unit (rms of the training targets)
+};
+constexpr int kMlpH = 128;   // hidden width
+constexpr int kLadder = 8;   // closed-form rungs sum_j c_j e^{-k j delta} of the density's remainder
+constexpr double kSurDecay = 0.7;  // network output j carries the weight kSurDecay^{n_j}
+constexpr int kMlpF = 4;     // continuous input features
+struct MlpNet {
+  int ncomp = 0, nout = 0;   // components (one-hot input), outputs
+  float* params = nullptr;   // device, flat: E A b1 W2 b2 W3 b3 W4 b4 (W[k][j]: input k -> output j)
+  int64_t off[9] = {0};
+  int64_t nparams = 0;
+};
+void mlp_layout(MlpNet& net);
+int gpu_mlp_forward(const MlpNet& net, const int32_t* comp, const float* feat, int64_t n, float* out,
+                    int ldo, int ocols, float* h1, float* h2, float* h3, hipStream_t st);
+int gpu_mlp_init(const MlpNet& net, uint64_t seed, hipStream_t st);
+int gpu_mlp_train(const MlpNet& net, const int32_t* comp, const float* feat, const float* y, int64_t n,
+                  int steps, int B, double lr, uint64_t seed, double* loss_first, double* loss_last,
+                  hipStream_t st);
+int gpu_mlp_grad(const MlpNet& net, const int32_t* comp, const float* feat, const float* y, int64_t n,
+                 float* grad, double* loss, hipStream_t st);
+// d_lad: ladder coefficients [surrogate component][kLadder] (device)
+int gpu_surrogate_samples(const Medium& md, const std::vector<CompInfo>& comps, const double* d_lad,
+                          const SurrogateDomain& dm, int nmax, uint64_t seed, int64_t n, int32_t* d_comp,
+                          float* d_feat, float* d_y, hipStream_t st, double* d_rz = nullptr);
+int gpu_surrogate_tables(const Medium& md, const std::vector<CompInfo>& comps,
+                         const std::vector<int32_t>& smap, const double* d_lad, const SurrogateDomain& dm,
+                         const std::vector<SommTask>& tasks, int nmax, const MlpNet& net, double* d_out,
+                         int64_t* n_used, hipStream_t st, int32_t* h_used);
+int gpu_surrogate_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
+                            const std::vector<int32_t>& smap, const double* d_lad, const SurrogateDomain& dm,
+                            const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
+                            int64_t npairs, const double* px, const double* py, const double* ph,
+                            const MlpNet& net, double* d_val, int64_t* n_fallback, hipStream_t st);
+
 // fmm.hip
 int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
                   const std::vector<int>& reac_task, const std::vector<double>& reac_phi,
@@ -202,7 +242,29 @@ int gpu_eval_one(fmmlm_plan_s* P, const double* q, double* phi, uint32_t parts, 
 
 void set_last_error(const std::string& s);
 
+// sides (layer, side) of a medium in the surrogate's numbering
+inline int side_index(int L, int layer, int side) {
+  // layer 0: side 1 only; layers 1..L-1: sides 1, 2; layer L: side 2 only
+  if (layer == 0) return 0;
+  if (layer == L) return 2 * L - 1;
+  return 1 + 2 * (layer - 1) + (side - 1);
+}
+
 }  // namespace fmmlm
+
+struct fmmlm_surrogate_s {
+  int L = 0;
+  std::vector<double> d, eps;
+  fmmlm::Medium medium;
+  int p = 0, nmax = 0;                 // outputs 2 nmax + 1, nmax = 2p
+  fmmlm::SurrogateDomain dm;
+  std::vector<fmmlm::CompInfo> comps;  // (2L)^2, index t * 2L + s
+  fmmlm::MlpNet net;
+  std::vector<double> lad;             // ladder coefficients [component][kLadder]
+  double* d_lad = nullptr;             // device copy
+  double ladder_fit = 0.0;             // largest weighted residual of the ladder fits
+  int device = 0;
+};
 
 #define FMM_HIP_TRY(expr)                                                      \
   do {                                                                         \

@@ -14,6 +14,7 @@
 // * Reaction near-field kernels (1/4pi) I_{00} for particle pairs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -201,14 +202,15 @@ __device__ void image_values(double amp, double S, double rho, double Z, int nma
 // sigma(k) - sinf e^{-k zinf}, which decays like e^{-k (zinf + 2 dmin)}, goes
 // through the quadrature.  With one interface the remainder is zero.
 __device__ void initial_values(const Medium& md, const Scatter& sc, const CompInfo& c, double S,
-                               double rho, double z, int nmax, double* out0, double* out1) {
+                               double rho, double z, int nmax, double* out0, double* out1,
+                               bool with_image = true) {
   constexpr int kMaxN = 2 * kPMax + 1;
   const bool want1 = (out1 != nullptr) && rho > 0.0;
   for (int n = 0; n <= nmax; ++n) {
     out0[n] = 0.0;
     if (out1 != nullptr) out1[n] = 0.0;
   }
-  image_values(c.sinf, S, rho, z + c.zinf, nmax, out0, want1 ? out1 : nullptr);
+  if (with_image) image_values(c.sinf, S, rho, z + c.zinf, nmax, out0, want1 ? out1 : nullptr);
   if (md.L < 2) return;
   double acc0[kMaxN], acc1[kMaxN];
   for (int n = 0; n <= nmax; ++n) acc0[n] = acc1[n] = 0.0;
@@ -321,6 +323,22 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
   }
 }
 
+// Orders M >= 2 of a table [cidx(n, m)] from M = 0, 1 by eq. recurrence.
+__device__ void recurrence_fill(double S, double rho, int nmax, double* o) {
+  // S^n I_{n,m+1} = (2m / a_{n+m}) (S / rho) S^{n-1} I_{n-1,m} - (a_{n-m} / a_{n+m}) S^n I_{n,m-1}
+  for (int m = 1; m + 1 <= nmax; ++m) {
+    for (int n = m + 1; n <= nmax; ++n) {
+      double v = 0.0;
+      if (rho > 0.0) {
+        const double anpm = sqrt((double)(n + m) * (n + m + 1));
+        const double anmm = sqrt((double)(n - m) * (n - m + 1));
+        v = (2.0 * m / anpm) * (S / rho) * o[cidx(n - 1, m)] - (anmm / anpm) * o[cidx(n, m - 1)];
+      }
+      o[cidx(n, m + 1)] = v;
+    }
+  }
+}
+
 // One thread per task: initial values, then eq. recurrence for M >= 2.
 __global__ void sommerfeld_table_kernel(Medium md, const CompInfo* __restrict__ comps,
                                         const SommTask* __restrict__ tasks, int ntask, int nmax,
@@ -339,18 +357,7 @@ __global__ void sommerfeld_table_kernel(Medium md, const CompInfo* __restrict__ 
     o[cidx(n, 0)] = i0[n];
     if (n >= 1) o[cidx(n, 1)] = i1[n];
   }
-  // S^n I_{n,m+1} = (2m / a_{n+m}) (S / rho) S^{n-1} I_{n-1,m} - (a_{n-m} / a_{n+m}) S^n I_{n,m-1}
-  for (int m = 1; m + 1 <= nmax; ++m) {
-    for (int n = m + 1; n <= nmax; ++n) {
-      double v = 0.0;
-      if (tk.rho > 0.0) {
-        const double anpm = sqrt((double)(n + m) * (n + m + 1));
-        const double anmm = sqrt((double)(n - m) * (n - m + 1));
-        v = (2.0 * m / anpm) * (tk.S / tk.rho) * o[cidx(n - 1, m)] - (anmm / anpm) * o[cidx(n, m - 1)];
-      }
-      o[cidx(n, m + 1)] = v;
-    }
-  }
+  recurrence_fill(tk.S, tk.rho, nmax, o);
 }
 
 __global__ void nearfield_kernel(Medium md, const CompInfo* __restrict__ comps,
@@ -368,6 +375,210 @@ __global__ void nearfield_kernel(Medium md, const CompInfo* __restrict__ comps,
   const double zeta = ph[a] + ph[b];
   double v0;
   initial_values(md, sc, comps[cmp[i]], 1.0, rho, zeta, 0, &v0, nullptr);
+  val[i] = v0 * (1.0 / (4.0 * 3.14159265358979323846));
+}
+
+// ---------------------------------------------------------------- learned form
+// The density's remainder sigma(k) e^{k zinf} - sinf is approximated first by a
+// ladder of exponentials sum_j c_j e^{-k j delta} (j = 1..kLadder, delta = 2 dmin,
+// fitted once per component), each rung integrating in closed form like the
+// leading term, as an image at zeta + zinf + j delta.  The network learns what
+// the ladder leaves.
+//
+// Counter-based generator (splitmix64 finaliser of seed, stream and counter).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline double rng_unit(uint64_t seed, uint64_t stream, uint64_t i) {
+  const uint64_t z = mix64(seed ^ mix64(stream + 0x9E3779B97F4A7C15ull * (i + 1)));
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+
+// Adds sign * sum_j c_j S^n P~_n^m / R_j^{n+1} (rungs at Z + j delta) to o0, o1.
+__device__ inline void ladder_values(const double* __restrict__ c, double delta, double sign, double S,
+                                     double rho, double Z, int nmax, double* o0, double* o1) {
+  for (int j = 0; j < kLadder; ++j)
+    image_values(sign * c[j], S, rho, Z + (j + 1) * delta, nmax, o0, o1);
+}
+
+// Network inputs for one (component, rho, zeta): with Z2 = zeta + zinf + 2 dmin
+// and R2 = |(rho, Z2)|, f = (2 rho/rho_max - 1, 2 zeta/zeta_max - 1,
+// 2 Z2/R2 - 1, 4 dmin/R2 - 1).  Returns R2.
+__device__ inline double surrogate_features(const SurrogateDomain& dm, double zinf, double rho,
+                                            double zeta, float4* f) {
+  const double Z2 = zeta + zinf + 2.0 * dm.dmin;
+  const double R2 = sqrt(rho * rho + Z2 * Z2);
+  f->x = (float)(2.0 * rho / dm.rho_max - 1.0);
+  f->y = (float)(2.0 * zeta / dm.zeta_max - 1.0);
+  f->z = (float)(2.0 * Z2 / R2 - 1.0);
+  f->w = (float)(4.0 * dm.dmin / R2 - 1.0);
+  return R2;
+}
+
+__device__ inline bool surrogate_in_domain(const SurrogateDomain& dm, double rho, double zeta) {
+  return rho >= 0.0 && rho <= dm.rho_max && zeta > 0.0 && zeta <= dm.zeta_max;
+}
+
+// Training samples: component uniform; (rho, zeta) half uniform over the
+// domain, half concentrated towards 0 (cubes of uniforms), where the
+// reaction near field and the finest M2L levels sit.  Target of output j
+// (degree n_j, order m_j: j <= nmax -> (j, 0), else (j - nmax, 1)) is what the
+// leading term and the ladder leave of the initial value (S = 1), times
+// kSurDecay^{n_j} R2^{n_j + 1} / yscale: the weights follow how fast an error
+// of degree n fades in the M2L result (the scaled multipole moments of a box
+// fall off like (0.87 S / R)^n, S <= R / 2).
+__global__ void surrogate_sample_kernel(Medium md, const CompInfo* __restrict__ comps, int ncomp,
+                                        const double* __restrict__ lad, SurrogateDomain dm, int nmax,
+                                        uint64_t seed, int64_t n, int32_t* __restrict__ comp_out,
+                                        float4* __restrict__ feat, float* __restrict__ y,
+                                        double* __restrict__ rz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Scatter sc;
+  local_coeffs(md, sc);
+  int c = (int)(rng_unit(seed, 1, i) * ncomp);
+  if (c >= ncomp) c = ncomp - 1;
+  double u = rng_unit(seed, 2, i), v = rng_unit(seed, 3, i);
+  if (rng_unit(seed, 4, i) < 0.5) {
+    u = u * u * u;
+    v = v * v * v;
+  }
+  const double rho = u * dm.rho_max;
+  const double zeta = fmax(v, 1e-6) * dm.zeta_max;
+  const CompInfo ci = comps[c];
+  float4 f;
+  const double R2 = surrogate_features(dm, ci.zinf, rho, zeta, &f);
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double i0[kMaxN], i1[kMaxN];
+  initial_values(md, sc, ci, 1.0, rho, zeta, nmax, i0, i1, false);
+  ladder_values(lad + (int64_t)c * kLadder, dm.delta, -1.0, 1.0, rho, zeta + ci.zinf, nmax, i0,
+                rho > 0.0 ? i1 : nullptr);
+  const int nout = 2 * nmax + 1;
+  float* yo = y + i * nout;
+  double pw = R2 / dm.yscale;  // kSurDecay^n R2^{n+1} / yscale
+  for (int nn = 0; nn <= nmax; ++nn) {
+    yo[nn] = (float)(i0[nn] * pw);
+    if (nn >= 1) yo[nmax + nn] = (float)(i1[nn] * pw);
+    pw *= R2 * kSurDecay;
+  }
+  comp_out[i] = c;
+  feat[i] = f;
+  if (rz) {
+    rz[2 * i] = rho;
+    rz[2 * i + 1] = zeta;
+  }
+}
+
+// Features of the plan's Sommerfeld tasks (rho, z of a task are unscaled).
+__global__ void surrogate_task_features_kernel(const CompInfo* __restrict__ comps,
+                                               const int32_t* __restrict__ smap, SurrogateDomain dm,
+                                               const SommTask* __restrict__ tasks, int ntask,
+                                               int32_t* __restrict__ comp_out, float4* __restrict__ feat) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const SommTask tk = tasks[t];
+  float4 f;
+  surrogate_features(dm, comps[tk.comp].zinf, tk.rho, tk.z, &f);
+  comp_out[t] = smap[tk.comp];
+  feat[t] = f;
+}
+
+// S^n I_{n,m} for a task: the leading term and the ladder in closed form plus
+// the network's remainder S^n yscale y_j / (kSurDecay^n R2^{n+1}) (FP32
+// network, FP64 here) for m = 0, 1; the quadrature when (rho, z) lies outside
+// the trained domain; then eq. recurrence.
+__global__ void surrogate_table_kernel(Medium md, const CompInfo* __restrict__ comps,
+                                       const int32_t* __restrict__ scomp, const double* __restrict__ lad,
+                                       SurrogateDomain dm, const SommTask* __restrict__ tasks, int ntask,
+                                       int nmax, const float* __restrict__ y, int ldy, int ynmax,
+                                       double* __restrict__ out, int32_t* __restrict__ used) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const SommTask tk = tasks[t];
+  const CompInfo c = comps[tk.comp];
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double i0[kMaxN], i1[kMaxN];
+  const bool net = surrogate_in_domain(dm, tk.rho, tk.z);
+  if (net) {
+    for (int n = 0; n <= nmax; ++n) i0[n] = i1[n] = 0.0;
+    double* o1 = tk.rho > 0.0 ? i1 : nullptr;
+    image_values(c.sinf, tk.S, tk.rho, tk.z + c.zinf, nmax, i0, o1);
+    ladder_values(lad + (int64_t)scomp[t] * kLadder, dm.delta, 1.0, tk.S, tk.rho, tk.z + c.zinf, nmax, i0,
+                  o1);
+    const double Z2 = tk.z + c.zinf + 2.0 * dm.dmin;
+    const double R2 = sqrt(tk.rho * tk.rho + Z2 * Z2);
+    const float* yy = y + (int64_t)t * ldy;
+    double pw = dm.yscale / R2;  // yscale S^n / (kSurDecay^n R2^{n+1})
+    for (int n = 0; n <= nmax; ++n) {
+      i0[n] += pw * (double)yy[n];
+      if (n >= 1 && tk.rho > 0.0) i1[n] += pw * (double)yy[ynmax + n];
+      pw *= tk.S / (R2 * kSurDecay);
+    }
+  } else {
+    Scatter sc;
+    local_coeffs(md, sc);
+    initial_values(md, sc, c, tk.S, tk.rho, tk.z, nmax, i0, i1);
+  }
+  double* o = out + (int64_t)t * ncoef(nmax);
+  for (int n = 0; n <= nmax; ++n) {
+    o[cidx(n, 0)] = i0[n];
+    if (n >= 1) o[cidx(n, 1)] = i1[n];
+  }
+  recurrence_fill(tk.S, tk.rho, nmax, o);
+  if (used) used[t] = net ? 1 : 0;
+}
+
+// Reaction near field through the network: per pair (component, rho, zeta)
+// and in-domain flag; out-of-domain pairs take the quadrature.
+__global__ void surrogate_pair_features_kernel(const CompInfo* __restrict__ comps,
+                                               const int32_t* __restrict__ smap, SurrogateDomain dm,
+                                               const int32_t* __restrict__ tpt, const int32_t* __restrict__ spt,
+                                               const int32_t* __restrict__ cmp, int64_t npairs,
+                                               const double* __restrict__ px, const double* __restrict__ py,
+                                               const double* __restrict__ ph, int32_t* __restrict__ comp_out,
+                                               float4* __restrict__ feat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  const int32_t a = tpt[i], b = spt[i];
+  const double dx = px[a] - px[b], dy = py[a] - py[b];
+  const double rho = sqrt(dx * dx + dy * dy);
+  const double zeta = ph[a] + ph[b];
+  float4 f;
+  surrogate_features(dm, comps[cmp[i]].zinf, rho, zeta, &f);
+  comp_out[i] = smap[cmp[i]];
+  feat[i] = f;
+}
+
+__global__ void surrogate_nearfield_kernel(Medium md, const CompInfo* __restrict__ comps,
+                                           const int32_t* __restrict__ scomp, const double* __restrict__ lad,
+                                           SurrogateDomain dm, const int32_t* __restrict__ tpt,
+                                           const int32_t* __restrict__ spt, const int32_t* __restrict__ cmp,
+                                           int64_t npairs, const double* __restrict__ px,
+                                           const double* __restrict__ py, const double* __restrict__ ph,
+                                           const float* __restrict__ y, int ldy, double* __restrict__ val,
+                                           unsigned long long* __restrict__ nfallback) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  const int32_t a = tpt[i], b = spt[i];
+  const double dx = px[a] - px[b], dy = py[a] - py[b];
+  const double rho = sqrt(dx * dx + dy * dy);
+  const double zeta = ph[a] + ph[b];
+  const CompInfo c = comps[cmp[i]];
+  double v0;
+  if (surrogate_in_domain(dm, rho, zeta)) {
+    v0 = 0.0;
+    image_values(c.sinf, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
+    ladder_values(lad + (int64_t)scomp[i] * kLadder, dm.delta, 1.0, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
+    const double Z2 = zeta + c.zinf + 2.0 * dm.dmin;
+    v0 += dm.yscale * (double)y[i * ldy] / sqrt(rho * rho + Z2 * Z2);
+  } else {
+    Scatter sc;
+    local_coeffs(md, sc);
+    initial_values(md, sc, c, 1.0, rho, zeta, 0, &v0, nullptr);
+    atomicAdd(nfallback, 1ull);
+  }
   val[i] = v0 * (1.0 / (4.0 * 3.14159265358979323846));
 }
 
@@ -512,6 +723,122 @@ int gpu_density(const Medium& md, const CompInfo& c, int64_t nk, const double* k
   FMM_HIP_TRY(hipStreamSynchronize(st));
   hipFree(buf);
   return FMMLM_OK;
+}
+
+int gpu_surrogate_samples(const Medium& md, const std::vector<CompInfo>& comps, const double* d_lad,
+                          const SurrogateDomain& dm, int nmax, uint64_t seed, int64_t n, int32_t* d_comp,
+                          float* d_feat, float* d_y, hipStream_t st, double* d_rz) {
+  if (n == 0) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  CompInfo* dc = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  surrogate_sample_kernel<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(
+      md, dc, (int)comps.size(), d_lad, dm, nmax, seed, n, d_comp, reinterpret_cast<float4*>(d_feat), d_y, d_rz);
+  FMM_HIP_TRY(hipGetLastError());
+  FMM_HIP_TRY(hipStreamSynchronize(st));
+  hipFree(dc);
+  return FMMLM_OK;
+}
+
+int gpu_surrogate_tables(const Medium& md, const std::vector<CompInfo>& comps,
+                         const std::vector<int32_t>& smap, const double* d_lad, const SurrogateDomain& dm,
+                         const std::vector<SommTask>& tasks, int nmax, const MlpNet& net, double* d_out,
+                         int64_t* n_used, hipStream_t st, int32_t* h_used) {
+  *n_used = 0;
+  if (tasks.empty()) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  const int nt = (int)tasks.size();
+  const int ynmax = (net.nout - 1) / 2;
+  CompInfo* dc = nullptr;
+  SommTask* dt = nullptr;
+  int32_t *dmap = nullptr, *dcomp = nullptr, *dused = nullptr;
+  float *dfeat = nullptr, *dy = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMalloc(&dt, tasks.size() * sizeof(SommTask)));
+  FMM_HIP_TRY(hipMalloc(&dmap, smap.size() * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&dcomp, nt * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&dused, nt * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&dfeat, (size_t)nt * 4 * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dy, (size_t)nt * net.nout * sizeof(float)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemcpyAsync(dt, tasks.data(), tasks.size() * sizeof(SommTask), hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemcpyAsync(dmap, smap.data(), smap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  surrogate_task_features_kernel<<<(nt + 63) / 64, 64, 0, st>>>(dc, dmap, dm, dt, nt, dcomp,
+                                                                reinterpret_cast<float4*>(dfeat));
+  FMM_HIP_TRY(hipGetLastError());
+  rc = gpu_mlp_forward(net, dcomp, dfeat, nt, dy, net.nout, net.nout, nullptr, nullptr, nullptr, st);
+  if (rc == FMMLM_OK) {
+    surrogate_table_kernel<<<(nt + 63) / 64, 64, 0, st>>>(md, dc, dcomp, d_lad, dm, dt, nt, nmax, dy, net.nout,
+                                                          ynmax, d_out, dused);
+    FMM_HIP_TRY(hipGetLastError());
+    std::vector<int32_t> used(nt);
+    FMM_HIP_TRY(hipMemcpyAsync(used.data(), dused, nt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FMM_HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t u : used) *n_used += u;
+    if (h_used) std::copy(used.begin(), used.end(), h_used);
+  }
+  hipFree(dc);
+  hipFree(dt);
+  hipFree(dmap);
+  hipFree(dcomp);
+  hipFree(dused);
+  hipFree(dfeat);
+  hipFree(dy);
+  return rc;
+}
+
+int gpu_surrogate_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
+                            const std::vector<int32_t>& smap, const double* d_lad, const SurrogateDomain& dm,
+                            const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
+                            int64_t npairs, const double* px, const double* py, const double* ph,
+                            const MlpNet& net, double* d_val, int64_t* n_fallback, hipStream_t st) {
+  *n_fallback = 0;
+  if (npairs == 0) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  constexpr int64_t kChunk = (int64_t)1 << 22;
+  const int64_t cap = std::min(npairs, kChunk);
+  CompInfo* dc = nullptr;
+  int32_t *dmap = nullptr, *dcomp = nullptr;
+  float *dfeat = nullptr, *dy = nullptr;
+  unsigned long long* dfb = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMalloc(&dmap, smap.size() * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&dcomp, cap * sizeof(int32_t)));
+  FMM_HIP_TRY(hipMalloc(&dfeat, cap * 4 * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dy, cap * sizeof(float)));
+  FMM_HIP_TRY(hipMalloc(&dfb, sizeof(unsigned long long)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemcpyAsync(dmap, smap.data(), smap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  FMM_HIP_TRY(hipMemsetAsync(dfb, 0, sizeof(unsigned long long), st));
+  for (int64_t o = 0; o < npairs && rc == FMMLM_OK; o += kChunk) {
+    const int64_t m = std::min(kChunk, npairs - o);
+    const unsigned nb = (unsigned)((m + 255) / 256);
+    surrogate_pair_features_kernel<<<nb, 256, 0, st>>>(dc, dmap, dm, d_tpt + o, d_spt + o, d_comp + o, m,
+                                                       px, py, ph, dcomp, reinterpret_cast<float4*>(dfeat));
+    FMM_HIP_TRY(hipGetLastError());
+    rc = gpu_mlp_forward(net, dcomp, dfeat, m, dy, 1, 1, nullptr, nullptr, nullptr, st);
+    if (rc) break;
+    surrogate_nearfield_kernel<<<nb, 256, 0, st>>>(md, dc, dcomp, d_lad, dm, d_tpt + o, d_spt + o, d_comp + o, m,
+                                                   px, py, ph, dy, 1, d_val + o, dfb);
+    FMM_HIP_TRY(hipGetLastError());
+  }
+  unsigned long long fb = 0;
+  if (rc == FMMLM_OK) {
+    FMM_HIP_TRY(hipMemcpyAsync(&fb, dfb, sizeof(fb), hipMemcpyDeviceToHost, st));
+    FMM_HIP_TRY(hipStreamSynchronize(st));
+  }
+  *n_fallback = (int64_t)fb;
+  hipFree(dc);
+  hipFree(dmap);
+  hipFree(dcomp);
+  hipFree(dfeat);
+  hipFree(dy);
+  hipFree(dfb);
+  return rc;
 }
 
 }  // namespace fmmlm

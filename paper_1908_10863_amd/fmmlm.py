@@ -28,7 +28,22 @@ _ERRORS = {
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("fp64_top_levels", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
-                ("mac_d2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("mac_d2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("surrogate", ctypes.c_void_p)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("nsamples", ctypes.c_int64), ("steps", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_int64), ("n_val", ctypes.c_int64), ("n_params", ctypes.c_int64),
+                ("n_components", ctypes.c_int32), ("n_outputs", ctypes.c_int32),
+                ("sample_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("val_rms", ctypes.c_double), ("val_max", ctypes.c_double),
+                ("yscale", ctypes.c_double), ("ladder_fit", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -43,13 +58,19 @@ class Stats(ctypes.Structure):
                 ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("tree_seconds", ctypes.c_double), ("lists_seconds", ctypes.c_double),
                 ("ops_seconds", ctypes.c_double), ("table_seconds", ctypes.c_double),
-                ("nearfield_seconds", ctypes.c_double)]
+                ("nearfield_seconds", ctypes.c_double), ("surrogate_tasks", ctypes.c_int64),
+                ("surrogate_pairs", ctypes.c_int64), ("surrogate_check", ctypes.c_double)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
            "fmm_layered_strerror", "fmm_layered_plan_stats", "fmm_layered_plan_tree",
            "fmm_layered_sommerfeld", "fmm_layered_density", "fmm_layered_profile_begin",
-           "fmm_layered_profile_end", "fmm_layered_density_asymptotic"]
+           "fmm_layered_profile_end", "fmm_layered_density_asymptotic",
+           "fmmlm_default_train_opts", "fmm_layered_surrogate_create",
+           "fmm_layered_surrogate_create_for_plan", "fmm_layered_surrogate_train",
+           "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
+           "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
+           "fmm_layered_surrogate_samples"]
 STAGES = ["gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "p2p_reaction", "combine"]
 
 _lib = None
@@ -98,6 +119,27 @@ def lib():
                                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                   dp, dp]
     L.fmm_layered_density_asymptotic.restype = ctypes.c_int
+    L.fmmlm_default_train_opts.argtypes = [ctypes.POINTER(TrainOpts)]
+    L.fmmlm_default_train_opts.restype = None
+    L.fmm_layered_surrogate_create.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.fmm_layered_surrogate_create.restype = ctypes.c_int
+    L.fmm_layered_surrogate_create_for_plan.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.fmm_layered_surrogate_create_for_plan.restype = ctypes.c_int
+    L.fmm_layered_surrogate_train.argtypes = [vp, ctypes.POINTER(TrainOpts), vp, ctypes.POINTER(TrainReport)]
+    L.fmm_layered_surrogate_train.restype = ctypes.c_int
+    L.fmm_layered_surrogate_destroy.argtypes = [vp]
+    L.fmm_layered_surrogate_destroy.restype = ctypes.c_int
+    L.fmm_layered_surrogate_params.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.fmm_layered_surrogate_params.restype = ctypes.c_int
+    L.fmm_layered_surrogate_grad.argtypes = [vp, ctypes.c_int64, vp, vp, vp, dp, vp, vp]
+    L.fmm_layered_surrogate_grad.restype = ctypes.c_int
+    L.fmm_layered_surrogate_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_double, ctypes.c_int64, vp, vp,
+                                             ctypes.c_int32, vp, vp, vp]
+    L.fmm_layered_surrogate_eval.restype = ctypes.c_int
+    L.fmm_layered_surrogate_samples.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp]
+    L.fmm_layered_surrogate_samples.restype = ctypes.c_int
     L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
     L.fmm_layered_profile_begin.restype = ctypes.c_int
     L.fmm_layered_profile_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -131,7 +173,7 @@ class Plan:
     """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
 
     def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
-                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None):
+                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None, surrogate=None):
         self.d = _host(d, np.float64)
         self.eps = _host(eps, np.float64)
         x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)
@@ -145,6 +187,8 @@ class Plan:
         o.max_rhs = max_rhs
         if mac_d2 is not None:
             o.mac_d2 = mac_d2
+        if surrogate is not None:
+            o.surrogate = surrogate._h
         h = ctypes.c_void_p()
         rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
                                     _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),
@@ -243,3 +287,91 @@ def density_asymptotic(d, eps, lt, ls, a, b):
     check(lib().fmm_layered_density_asymptotic(len(d), _ptr(d), _ptr(eps), lt, ls, a, b,
                                                ctypes.byref(si), ctypes.byref(zi)))
     return si.value, zi.value
+
+
+class Surrogate:
+    """Learned form: fmm_layered_surrogate_* on a medium (or a plan's medium and domain)."""
+
+    def __init__(self, d=None, eps=None, p=None, rho_max=None, zeta_max=None, seed=1, plan=None):
+        h = ctypes.c_void_p()
+        if plan is not None:
+            check(lib().fmm_layered_surrogate_create_for_plan(plan._h, seed, ctypes.byref(h)))
+            p = plan.p
+        else:
+            d = _host(d, np.float64)
+            eps = _host(eps, np.float64)
+            check(lib().fmm_layered_surrogate_create(len(d), _ptr(d), _ptr(eps), p, float(rho_max),
+                                                     float(zeta_max), seed, ctypes.byref(h)))
+        self._h = h
+        self.nout = 4 * p + 1
+
+    def train(self, nsamples=None, steps=None, batch=None, lr=None, seed=None, stream=None) -> dict:
+        o = TrainOpts()
+        lib().fmmlm_default_train_opts(ctypes.byref(o))
+        for k, v in (("nsamples", nsamples), ("steps", steps), ("batch", batch), ("lr", lr),
+                     ("seed", seed)):
+            if v is not None:
+                setattr(o, k, v)
+        r = TrainReport()
+        check(lib().fmm_layered_surrogate_train(self._h, ctypes.byref(o), _stream_handle(stream),
+                                                ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in TrainReport._fields_}
+
+    def params(self, set_to=None) -> np.ndarray:
+        n = ctypes.c_int64()
+        check(lib().fmm_layered_surrogate_params(self._h, None, None, ctypes.byref(n)))
+        if set_to is not None:
+            v = _host(set_to, np.float32)
+            if v.size != n.value:
+                raise ValueError("wrong parameter count")
+            check(lib().fmm_layered_surrogate_params(self._h, None, _ptr(v), ctypes.byref(n)))
+        out = np.zeros(n.value, np.float32)
+        check(lib().fmm_layered_surrogate_params(self._h, _ptr(out), None, ctypes.byref(n)))
+        return out
+
+    def grad(self, comp, feat, target, stream=None):
+        """(loss, gradient) of the mean squared error over one batch, on the GPU."""
+        comp = _host(comp, np.int32)
+        feat = _host(feat, np.float32)
+        target = _host(target, np.float32)
+        n = len(comp)
+        g = np.zeros(self.params().size, np.float32)
+        loss = ctypes.c_double()
+        check(lib().fmm_layered_surrogate_grad(self._h, n, _ptr(comp), _ptr(feat), _ptr(target),
+                                               ctypes.byref(loss), _ptr(g), _stream_handle(stream)))
+        return loss.value, g
+
+    def samples(self, n, seed=1, stream=None):
+        """The training samples for seed: (comp, rho, zeta, feat [n, 4], target [n, nout])."""
+        nout = self.nout
+        comp = np.zeros(n, np.int32)
+        rho = np.zeros(n)
+        zeta = np.zeros(n)
+        feat = np.zeros((n, 4), np.float32)
+        target = np.zeros((n, nout), np.float32)
+        check(lib().fmm_layered_surrogate_samples(self._h, n, seed, _ptr(comp), _ptr(rho), _ptr(zeta),
+                                                  _ptr(feat), _ptr(target), _stream_handle(stream)))
+        return comp, rho, zeta, feat, target
+
+    def eval(self, lt, ls, a, b, S, rho, z, nmax, stream=None):
+        """S^N I_{N,M} like sommerfeld(), through the network; also the served-by-network flags."""
+        rho = _host(np.atleast_1d(rho), np.float64)
+        z = _host(np.atleast_1d(z), np.float64)
+        nc = (nmax + 1) * (nmax + 2) // 2
+        out = np.zeros((len(rho), nc))
+        used = np.zeros(len(rho), np.int32)
+        check(lib().fmm_layered_surrogate_eval(self._h, lt, ls, a, b, float(S), len(rho), _ptr(rho),
+                                               _ptr(z), nmax, _ptr(out), _ptr(used),
+                                               _stream_handle(stream)))
+        return out, used
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fmm_layered_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

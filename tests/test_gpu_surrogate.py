@@ -1,0 +1,232 @@
+"""Learned form: image ladder + MLP surrogate of the reaction Sommerfeld integrals.
+
+* The training kernels' gradient (FP32, GPU) against the oracle's FP64 chain
+  rule at the same parameters: relative L2 difference <= 2e-5 per parameter block.
+* Training on the quadrature's samples for the 6-region medium: held-out error
+  and the quadrature's own check inside a plan.
+* Tables at M2L geometry (rho = 0 or rho >= S, S <= 0.4 R1) against the
+  quadrature, in interaction units R1 max_{N,M} 0.87^N |difference|, for the
+  ladder alone (network zeroed) and for ladder + network.
+* The FMM with the learned form against the direct-sum oracle: relative L2 <= 1e-5.
+* Fallback: outside the trained domain the quadrature serves, bit for bit.
+* Gain: time of the Sommerfeld initial values and of the reaction near field with
+  and without the learned form (printed, and asserted to be a real speed-up).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+D3 = [0.0, -1.0]
+E3 = [1.0, 5.0, 2.0]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1908_10863_amd import fmmlm
+    fmmlm.lib()
+    return fmmlm
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1908_10863_amd import workloads
+    return workloads
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_gradient_matches_oracle(dev, F):
+    from oracle import mlp
+    _say("surrogate gradient vs oracle")
+    s = F.Surrogate(D3, E3, p=4, rho_max=1.5, zeta_max=2.2, seed=3)
+    theta = s.params()
+    ncomp = 16
+    nout = 17
+    lay = mlp.layout(ncomp, nout)
+    assert theta.size == lay["total"]
+    rng = np.random.default_rng(4)
+    n = 200  # three full tiles of 64 and a ragged one
+    comp = rng.integers(0, ncomp, n).astype(np.int32)
+    feat = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    y = rng.normal(0, 0.3, (n, nout)).astype(np.float32)
+    loss, g = s.grad(comp, feat, y)
+    L, gref = mlp.loss_and_grad(theta.astype(np.float64), ncomp, nout, comp, feat.astype(np.float64),
+                                y.astype(np.float64))
+    assert abs(loss - L) <= 1e-5 * L
+    for name in ("E", "A", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        o, shp = lay[name]
+        k = int(np.prod(shp))
+        a, b = g[o:o + k].astype(np.float64), gref[o:o + k]
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        _say(f"  {name}: rel {e:.2e}")
+        assert e <= 2e-5, name
+
+
+def test_params_roundtrip_and_validation(dev, F):
+    s = F.Surrogate(D3, E3, p=3, rho_max=1.0, zeta_max=1.0, seed=5)
+    th = s.params()
+    th2 = (th * 0.5 + 0.01).astype(np.float32)
+    assert np.array_equal(s.params(th2), th2)
+    with pytest.raises(ValueError):
+        s.params(th2[:-1])
+    with pytest.raises(NotImplementedError):
+        F.Surrogate([0.0], [1.0, 2.0], p=3, rho_max=1.0, zeta_max=1.0)
+    with pytest.raises(ValueError):
+        s.grad(np.array([16], np.int32), np.zeros((1, 4), np.float32), np.zeros((1, 13), np.float32))
+
+
+@pytest.fixture(scope="module")
+def trained(dev, F, W):
+    """Surrogate for the 6-region medium over the domain of a plan of that medium."""
+    w = W.config(4, n=20000)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=64)
+    s = F.Surrogate(plan=plan, seed=11)
+    plan.close()
+    rep = s.train()
+    _say(f"  train: {rep}")
+    return s, rep, w
+
+
+def test_training_converges(trained):
+    s, rep, w = trained
+    assert rep["n_train"] + rep["n_val"] == 2097152
+    assert rep["n_components"] == 100 and rep["n_outputs"] == 41
+    assert rep["ladder_fit"] < 1e-2
+    assert rep["loss_last"] < 0.1 * rep["loss_first"]
+    assert rep["val_rms"] < 0.3
+
+
+@pytest.fixture(scope="module")
+def ladder_only(trained, F):
+    """The same ladder with the network zeroed (its output is exactly 0)."""
+    s, rep, w = trained
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=64)
+    z = F.Surrogate(plan=plan, seed=11)
+    plan.close()
+    z.params(np.zeros_like(s.params()))
+    return z
+
+
+def _m2l_geometry(rng, n):
+    """(rho, z, S) as M2L tasks have them: rho = 0 or rho >= S, and S <= 0.4 R."""
+    rho = rng.uniform(0, 1.4, n)
+    rho[: n // 8] = 0.0
+    z = rng.uniform(0.05, 2.0, n)
+    S = 0.4 * np.hypot(rho, z)
+    S = np.where(rho > 0, np.minimum(S, rho), S)
+    return rho, z, S
+
+
+def _interaction_error(got, ref, R1, nmax):
+    nn = np.array([n for n in range(nmax + 1) for m in range(n + 1)])
+    return float((np.abs(got - ref) * 0.87 ** nn * R1).max())
+
+
+def test_tables_against_quadrature_and_fallback(trained, ladder_only, F):
+    s, rep, w = trained
+    d, eps = w["d"], w["eps"]
+    rng = np.random.default_rng(2)
+    rho, z, S = _m2l_geometry(rng, 160)
+    worst = {"ladder": 0.0, "ladder+net": 0.0}
+    for (lt, ls, a, b) in [(0, 0, 1, 1), (2, 3, 2, 1), (5, 1, 2, 2), (1, 4, 1, 2), (3, 3, 1, 2)]:
+        zi = F.density_asymptotic(d, eps, lt, ls, a, b)[1]
+        for i in range(len(rho)):
+            ref = F.sommerfeld(d, eps, lt, ls, a, b, S[i], rho[i:i + 1], z[i:i + 1], 20)
+            R1 = np.hypot(rho[i], z[i] + zi)
+            for tag, sur in (("ladder", ladder_only), ("ladder+net", s)):
+                got, used = sur.eval(lt, ls, a, b, S[i], rho[i:i + 1], z[i:i + 1], 20)
+                assert used.all()
+                worst[tag] = max(worst[tag], _interaction_error(got, ref, R1, 20))
+    _say(f"  worst interaction error: ladder {worst['ladder']:.2e}, ladder+net {worst['ladder+net']:.2e}")
+    assert worst["ladder+net"] < 1e-5
+    assert worst["ladder+net"] < worst["ladder"]
+    # outside the domain the quadrature serves: identical values
+    far = np.array([5.0, 0.3])
+    zz = np.array([0.5, 9.0])
+    got, used = s.eval(1, 1, 1, 1, 1.0, far, zz, 20)
+    ref = F.sommerfeld(d, eps, 1, 1, 1, 1, 1.0, far, zz, 20)
+    assert not used.any()
+    assert np.array_equal(got, ref)
+
+
+def test_fmm_with_surrogate_vs_oracle(trained, ladder_only, F, W, oracle_mod):
+    s, rep, w0 = trained
+    _say("FMM with the learned form vs oracle")
+    w = W.config(4, n=1500, seed=77)
+    t = np.arange(0, 1500, 25)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                               targets=t, method="quad")
+    import torch
+    q = torch.tensor(w["q"][0], device="cuda:0")
+    errs = {}
+    for tag, sur in (("quadrature", None), ("ladder", ladder_only), ("ladder+net", s)):
+        plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=20,
+                      surrogate=sur)
+        st = plan.stats()
+        phi = plan.eval(q).cpu().numpy()
+        plan.close()
+        errs[tag] = relerr(phi[t], ref)
+        _say(f"  {tag}: rel L2 {errs[tag]:.3e} tasks {st['n_sommerfeld_tasks']} "
+             f"learned tasks {st['surrogate_tasks']} pairs {st['surrogate_pairs']}/{st['p2p_reaction_pairs']} "
+             f"check {st['surrogate_check']:.2e}")
+        if sur is not None:
+            assert st["surrogate_tasks"] > 0.9 * st["n_sommerfeld_tasks"]
+        if sur is s:
+            assert st["surrogate_check"] < 1e-5
+    assert errs["quadrature"] < 1e-6
+    assert errs["ladder+net"] < 1e-5
+
+
+def test_gain_over_quadrature(trained, F, W):
+    """What the network buys: initial values of the Sommerfeld integrals and the
+    reaction near field at plan time, network vs quadrature."""
+    s, rep, w = trained
+    d, eps = w["d"], w["eps"]
+    rng = np.random.default_rng(8)
+    n = 200000
+    rho = rng.uniform(0, 1.4, n)
+    z = rng.uniform(0.01, 2.0, n)
+    out = {}
+    for nmax in (20, 0):
+        F.sommerfeld(d, eps, 2, 3, 2, 1, 1.0, rho[:1000], z[:1000], nmax)
+        s.eval(2, 3, 2, 1, 1.0, rho[:1000], z[:1000], nmax)
+        t0 = time.perf_counter()
+        F.sommerfeld(d, eps, 2, 3, 2, 1, 1.0, rho, z, nmax)
+        tq = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s.eval(2, 3, 2, 1, 1.0, rho, z, nmax)
+        tn = time.perf_counter() - t0
+        out[nmax] = (tq, tn)
+        _say(f"  nmax={nmax}: quadrature {tq * 1e3:.1f} ms, network {tn * 1e3:.1f} ms, x{tq / tn:.1f}")
+    assert out[20][0] > 3.0 * out[20][1]
+    # plan time of a plan with a large reaction near field (dense points near the interfaces)
+    wn = W.config(4, n=65536, seed=5)
+    res = {}
+    for tag, sur in (("quadrature", None), ("surrogate", s)):
+        plan = F.Plan(wn["d"], wn["eps"], wn["x"], wn["y"], wn["z"], wn["layer"], p=10, leaf_cap=128,
+                      precision=1, mac_d2=4, surrogate=sur)
+        st = plan.stats()
+        plan.close()
+        res[tag] = st
+        _say(f"  {tag}: plan {st['plan_seconds']:.3f}s tables {st['table_seconds']:.3f}s "
+             f"near field {st['nearfield_seconds']:.3f}s pairs {st['p2p_reaction_pairs']}")
+    assert res["surrogate"]["nearfield_seconds"] < 0.5 * res["quadrature"]["nearfield_seconds"]
