@@ -83,7 +83,8 @@ def main():
     ap.add_argument("--leaf-cap-fp64", type=int, default=128)
     ap.add_argument("--mac", type=int, default=4)
     ap.add_argument("--rhs", type=int, default=1, help="charge vectors per evaluation (batched form)")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle targets for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="oracle targets: the CPU baseline and the error subsample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "

@@ -720,6 +720,10 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     rptr[li + 1] = (int32_t)(rsrc.size() / 2);
   }
+  std::vector<int32_t> plv;
+  for (int64_t li = 0; li < P->nleaves; ++li)
+    if (pptr[li + 1] > pptr[li]) plv.push_back((int32_t)li);
+  P->n_pl_leaves = (int64_t)plv.size();
   P->stats.p2p_free_pairs = B.free_pairs;
   P->stats.p2p_reaction_pairs = B.reac_pairs;
   // ---- leaf of every tree point, free-space point ranges
@@ -764,7 +768,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(bcx, bcx); UP(bcy, bcy); UP(bch, bch); UP(blevel, blevel); UP(bstart, bstart); UP(bcount, bcount);
   UP(bparent, bparent); UP(bchild0, bchild0); UP(bnchild, bnchild); UP(leaves, leaves);
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
-  UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
+  UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(pl_leaves, plv); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
   UP(coefA, coefA); UP(sc_levels, scl);
   UP(tile_ptr, tptr); UP(tile_tgt, ttgt); UP(tile_level, tlev); UP(step_op, sop); UP(step_src, ssrc);
   UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind);

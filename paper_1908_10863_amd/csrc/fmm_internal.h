@@ -136,6 +136,8 @@ struct fmmlm_plan_s {
   // P2P free, CSR over leaves
   int32_t *p2p_ptr = nullptr;      // [nleaves + 1]
   int32_t *p2p_src = nullptr;      // [2 * entries] (start, count)
+  int32_t *pl_leaves = nullptr;    // leaf list indices with free-space P2P entries
+  int64_t n_pl_leaves = 0;
   // P2P reaction, CSR over leaves
   int32_t *rp_ptr = nullptr;       // [nleaves + 1]
   int32_t *rp_src = nullptr;       // [2 * entries] (start, count)
