@@ -22,12 +22,20 @@ PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published), FLOP/s
 
 
-def stage_flops(stats, p, stage):
-    """Algorithmic floating-point work of one launch of a stage (see the design notes)."""
+def stage_flops(stats, p, stage, rhs=1):
+    """Algorithmic floating-point work of one evaluation of a stage over `rhs` charge vectors:
+    the dense real-form operator counts (p+1)^2 x (p+1)^2 multiply-adds per box pair and vector."""
+    return rhs * _stage_flops1(stats, p, stage)
+
+
+def _stage_flops1(stats, p, stage):
     full = (p + 1) ** 2
+    pairs = stats["m2l_free_pairs"] + stats["m2l_reaction_pairs"]
     if stage == "m2l":
-        # dense real-form operator: (p+1)^2 x (p+1)^2 multiply-adds per box pair
-        return 2.0 * full * full * (stats["m2l_free_pairs"] + stats["m2l_reaction_pairs"])
+        # the main M2L GEMM launch: every pair below the levels kept in FP64
+        return 2.0 * full * full * (pairs - stats["m2l_top_pairs"])
+    if stage == "m2l_top":
+        return 2.0 * full * full * stats["m2l_top_pairs"]
     if stage == "p2p_free":
         return 11.0 * stats["p2p_free_pairs"]
     if stage == "p2p_reaction":
@@ -108,7 +116,7 @@ def main():
     st = form["stats"]
     avg = form["stages"]
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
-    flops = stage_flops(st, p, dom)
+    flops = stage_flops(st, p, dom, args.rhs)
     achieved = flops / (avg[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,

@@ -73,7 +73,13 @@ typedef struct {
                               only if their centres are at least sqrt(mac_d2) box sizes apart
                               (and not adjacent); 4 is the classic one-box separation.
                               Range 4..12, default 6 */
-  int32_t reserved[3];     /* must be 0 */
+  int32_t graph;           /* 1: fmm_layered_eval captures its kernel launches into a HIP graph
+                              on the first call and replays the graph while nrhs, q, ldq, phi,
+                              ldphi, parts and the stream stay the same (a change captures
+                              anew).  Needs a stream other than the null stream (on the null
+                              stream evaluations launch directly).  Not used while profiling.
+                              Default 0 */
+  int32_t reserved[2];     /* must be 0 */
   fmmlm_surrogate_t surrogate; /* learned form (default NULL = quadrature): a trained network
                               for this medium serves the reaction Sommerfeld initial values
                               and near-field kernels inside its domain, the quadrature the
@@ -171,6 +177,11 @@ typedef struct {
                                     tasks: the largest R1 max_{N,M} 0.87^N |difference of
                                     S^N I_{N,M}|, R1 = |(rho, z + zinf)| (the error relative to
                                     the interaction 1/R1 that the operator carries) */
+  int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one tile) ... */
+  int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
+                                    (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
+  int32_t reserved_stats;
+  int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64 (0 otherwise) */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
@@ -339,13 +350,17 @@ int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const 
  * Live per-stage timing of evaluations (benchmarks).  profile_begin makes the
  * next max_evals evaluations of the plan record a HIP event on their stream
  * before the first stage and after every stage (FMMLM_NSTAGES stages, in the
- * order gather, P2M, M2M, M2L, L2L, L2P, P2P free, P2P reaction, combine).
+ * order gather, P2M, M2M, M2L top, M2L, M2L reduce, L2L, L2P, P2P free,
+ * P2P reaction, combine).  "M2L" is one kernel launch: the main M2L GEMM (the
+ * matrix-core kernel below the FP64 levels in the FP32 form, the FP64 kernel
+ * over every level otherwise); "M2L top" clears the local expansions and, in
+ * the FP32 form, runs the FP64 levels and converts the multipole expansions.
  * profile_end synchronises the device, writes the summed milliseconds of each
  * stage over the recorded evaluations to stage_ms[FMMLM_NSTAGES] (host), the
  * number of recorded evaluations to *n_evals, and stops recording.
  * Errors: FMMLM_EINVAL, FMMLM_EDEVICE, FMMLM_ENOMEM.
  */
-#define FMMLM_NSTAGES 9
+#define FMMLM_NSTAGES 11
 int fmm_layered_profile_begin(fmmlm_plan_t plan, int32_t max_evals);
 int fmm_layered_profile_end(fmmlm_plan_t plan, double* stage_ms, int64_t* n_evals);
 

@@ -25,6 +25,8 @@
 #include <chrono>
 #include <unordered_set>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -282,7 +284,14 @@ double coefA_host(int n, int m) {
   return ((n & 1) ? -1.0 : 1.0) * cn / std::sqrt(std::tgamma(n - m + 1.0) * std::tgamma(n + m + 1.0));
 }
 
+void drop_graph(fmmlm_plan_s* P) {
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  P->gexec = nullptr;
+  P->gkey = GraphKey{};
+}
+
 void free_plan(fmmlm_plan_s* P) {
+  drop_graph(P);
   if (!P) return;
   for (auto e : P->prof_ev) (void)hipEventDestroy(e);
   for (auto& b : P->bufs) hipFree(b.ptr);
@@ -616,10 +625,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->n_free_ops = nfreeops;
     P->nops = nfreeops + (int64_t)B.reac_task.size();
   }
-  // ---- M2L tiles: up to tile_cols target boxes of one level, tree and octant
-  // class per tile (boxes of one class share their interaction offsets); one
-  // step per operator (free space or reaction) present in the tile
-  std::vector<int32_t> tptr(1, 0), ttgt, tlev, sop, skind, ssrc, us, tuptr;
+  // ---- M2L tiles: up to tile_cols target boxes per tile; one step per
+  // operator present in the tile
+  std::vector<int32_t> tptr(1, 0), ttgt, tlev, sop, skind, ssrc, smask, us, umask, tuptr;
   {
     {
       const int nr0 = (P->p + 1) * (P->p + 1);
@@ -633,58 +641,107 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     const int nfo = (int)P->n_free_ops;
     std::vector<int> slot(std::max<int64_t>(P->nops, 1), -1);
     std::vector<int> used;
-    for (int l = 0; l <= P->maxlev; ++l) {
-      std::vector<std::vector<int32_t>> bucket((size_t)nt * 8);
-      for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
-        if (mptr[b + 1] > mptr[b]) {
+    // Four groups of tiles, in this order: free space on the FP64 levels,
+    // reaction on the FP64 levels, free space on the other levels, reaction on
+    // the other levels (in the FP64 form every level is an FP64 level).  Within
+    // a group every target box is in at most one tile.  Free-space tiles hold
+    // boxes of one tree, level and octant class (boxes of one class share their
+    // offsets); reaction tiles hold boxes of one tree, level, xy parity and
+    // height row, since a reaction operator depends on the heights of both
+    // boxes above their interfaces.  Inside a bucket, boxes with the same
+    // operator set are put next to each other.
+    const int k64 = P->fp32 ? P->opts.fp64_top_levels : P->maxlev + 1;
+    P->tile_grp[0] = 0;
+    for (int grp = 0; grp < 4; ++grp) {
+      const bool reac = (grp & 1) != 0;
+      for (int l = 0; l <= P->maxlev; ++l) {
+        if ((l < k64) != (grp < 2)) continue;
+        std::vector<std::tuple<uint64_t, uint64_t, int32_t>> key;  // (bucket, operator-set hash, box)
+        std::vector<int> ops;
+        for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b) {
+          ops.clear();
+          for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
+            const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
+            if ((op >= nfo) == reac) ops.push_back(op);
+          }
+          if (ops.empty()) continue;
+          std::sort(ops.begin(), ops.end());
+          uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted operator ids
+          for (int op : ops) {
+            h ^= (uint64_t)(uint32_t)op;
+            h *= 1099511628211ull;
+          }
           const HBox& bx = B.boxes[b];
-          bucket[(size_t)bx.tree * 8 + ((bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2))].push_back(
-              (int32_t)b);
+          const uint64_t cls = reac ? (uint64_t)((bx.ix & 1) | ((bx.iy & 1) << 1)) << 32 | (uint64_t)bx.ih
+                                    : (uint64_t)((bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2)) << 32;
+          key.emplace_back(((uint64_t)bx.tree << 56) | cls, h, (int32_t)b);
         }
-      for (const auto& tg : bucket)
-        for (size_t c0 = 0; c0 < tg.size(); c0 += TBc) {
-          const size_t nc_ = std::min<size_t>(TBc, tg.size() - c0);
-          tlev.push_back(l);
-          for (size_t c = 0; c < (size_t)TBc; ++c) ttgt.push_back(c < nc_ ? tg[c0 + c] : -1);
-          used.clear();
-          std::vector<std::vector<int32_t>> cols;
-          for (size_t c = 0; c < nc_; ++c) {
-            const int32_t b = tg[c0 + c];
-            for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
-              const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
-              if (slot[op] < 0) {
-                slot[op] = (int)cols.size();
-                cols.emplace_back(TBc, -1);
-                used.push_back(op);
+        std::sort(key.begin(), key.end());
+        // consecutive runs of TBc boxes: small buckets share a tile (the kernels
+        // skip the column groups a step leaves empty)
+        {
+          const size_t k0 = 0, k1 = key.size();
+          for (size_t c0 = k0; c0 < k1; c0 += TBc) {
+            const size_t nc_ = std::min<size_t>(TBc, k1 - c0);
+            tlev.push_back(l);
+            for (size_t c = 0; c < (size_t)TBc; ++c) ttgt.push_back(c < nc_ ? std::get<2>(key[c0 + c]) : -1);
+            used.clear();
+            std::vector<std::vector<int32_t>> cols;
+            for (size_t c = 0; c < nc_; ++c) {
+              const int32_t b = std::get<2>(key[c0 + c]);
+              for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
+                const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
+                if ((op >= nfo) != reac) continue;
+                if (slot[op] < 0) {
+                  slot[op] = (int)cols.size();
+                  cols.emplace_back(TBc, -1);
+                  used.push_back(op);
+                }
+                cols[slot[op]][c] = msrc[e];
               }
-              cols[slot[op]][c] = msrc[e];
             }
+            std::sort(used.begin(), used.end());
+            for (int op : used) {
+              sop.push_back(op);
+              skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
+              const std::vector<int32_t>& cv = cols[slot[op]];
+              ssrc.insert(ssrc.end(), cv.begin(), cv.end());
+              uint32_t msk = 0;  // bit g: a source in columns [8 g, 8 g + 8)
+              for (int c = 0; c < TBc; ++c)
+                if (cv[c] >= 0) {
+                  msk |= 1u << (c >> 3);
+                  if (P->fp32 && grp < 2) ++P->stats.m2l_top_pairs;
+                }
+              smask.push_back((int32_t)msk);
+            }
+            for (int op : used) slot[op] = -1;
+            tptr.push_back((int32_t)sop.size());
           }
-          std::sort(used.begin(), used.end());
-          for (int op : used) {
-            sop.push_back(op);
-            skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
-            ssrc.insert(ssrc.end(), cols[slot[op]].begin(), cols[slot[op]].end());
-          }
-          for (int op : used) slot[op] = -1;
-          tptr.push_back((int32_t)sop.size());
         }
+      }
+      P->tile_grp[grp + 1] = (int64_t)tlev.size();
     }
     P->ntiles = (int64_t)tlev.size();
     P->nsteps = (int64_t)sop.size();
-    P->tile_split = 0;
-    while (P->tile_split < P->ntiles && tlev[P->tile_split] < P->opts.fp64_top_levels) ++P->tile_split;
-    // work units of at most kStepsPerUnit steps
+    P->stats.m2l_steps = P->nsteps;
+    P->stats.m2l_tile_cols = TBc;
+    // work units of at most kStepsPerUnit steps; units [0, unit_split) belong
+    // to the tiles on FP64 levels (groups 0 and 1)
     constexpr int kStepsPerUnit = 16;
     tuptr.assign(1, 0);
     for (int64_t t = 0; t < P->ntiles; ++t) {
+      if (t == P->tile_grp[2]) P->unit_split = (int64_t)(us.size() / 2);
       for (int32_t a = tptr[t]; a < tptr[t + 1]; a += kStepsPerUnit) {
+        const int32_t b = std::min(a + kStepsPerUnit, tptr[t + 1]);
         us.push_back(a);
-        us.push_back(std::min(a + kStepsPerUnit, tptr[t + 1]));
+        us.push_back(b);
+        int32_t um = 0;  // column groups any step of the unit touches
+        for (int32_t q = a; q < b; ++q) um |= smask[q];
+        umask.push_back(um);
       }
       tuptr.push_back((int32_t)(us.size() / 2));
-      if (t + 1 == P->tile_split) P->unit_split = (int64_t)(us.size() / 2);
     }
+    if (P->ntiles == P->tile_grp[2]) P->unit_split = (int64_t)(us.size() / 2);
     P->nunits = (int64_t)(us.size() / 2);
     // operator tables must fit a budget (FP64 + FP32 copies)
     const double tbytes = (double)P->nops * P->nrk * 32.0 * P->mrt * (P->fp32 ? 12.0 : 8.0);
@@ -771,7 +828,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(pl_leaves, plv); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
   UP(coefA, coefA); UP(sc_levels, scl);
   UP(tile_ptr, tptr); UP(tile_tgt, ttgt); UP(tile_level, tlev); UP(step_op, sop); UP(step_src, ssrc);
-  UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind);
+  UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind); UP(step_mask, smask); UP(unit_mask, umask);
   if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) return rc;
 #undef UP
   P->stats.lists_seconds = seconds_since(tphase);
@@ -1031,8 +1088,9 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   if (o.leaf_cap < 1 || o.max_rhs < 1) return FMMLM_EINVAL;
   if (o.mac_d2 < 4 || o.mac_d2 > 12) return FMMLM_EINVAL;
   if (o.precision != FMMLM_FP64 && o.precision != FMMLM_FP32_COMPENSATED) return FMMLM_EINVAL;
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (o.reserved[i] != 0) return FMMLM_EINVAL;
+  if (o.graph != 0 && o.graph != 1) return FMMLM_EINVAL;
   if (o.fp64_top_levels < 0 || o.fp64_top_levels > kMaxLevel + 1) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (o.surrogate) {
@@ -1110,19 +1168,53 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   if (ldq < plan->N || ldphi < plan->N) return FMMLM_EINVAL;
   if (parts == 0 || (parts & ~(FMMLM_FREE | FMMLM_REACTION))) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (nrhs == 1) {
-    hipEvent_t* ev = nullptr;
-    if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
-    return gpu_eval_one(plan, q, phi, parts, st, ev);
+  auto launch = [&]() -> int {
+    if (nrhs == 1) {
+      hipEvent_t* ev = nullptr;
+      if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
+      return gpu_eval_one(plan, q, phi, parts, st, ev);
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += plan->gmax) {
+      const int g = std::min(plan->gmax, nrhs - r0);
+      hipEvent_t* ev = nullptr;
+      if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
+      int rc = gpu_eval_batch(plan, g, q + (int64_t)r0 * ldq, ldq, phi + (int64_t)r0 * ldphi, ldphi, parts, st, ev);
+      if (rc) return rc;
+    }
+    return FMMLM_OK;
+  };
+  const bool profiling = plan->prof_used < plan->prof_cap;
+  if (!plan->opts.graph || st == nullptr || profiling) return launch();
+  // graph mode: replay while the arguments are the same, capture anew otherwise
+  const GraphKey key{nrhs, q, ldq, phi, ldphi, parts, st};
+  if (plan->gexec && plan->gkey == key) {
+    FMM_HIP_TRY(hipGraphLaunch(plan->gexec, st));
+    return FMMLM_OK;
   }
-  for (int r0 = 0; r0 < nrhs; r0 += plan->gmax) {
-    const int g = std::min(plan->gmax, nrhs - r0);
-    hipEvent_t* ev = nullptr;
-    if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
-    int rc = gpu_eval_batch(plan, g, q + (int64_t)r0 * ldq, ldq, phi + (int64_t)r0 * ldphi, ldphi, parts, st, ev);
-    if (rc) return rc;
+  drop_graph(plan);
+  FMM_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = launch();
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc == FMMLM_OK && e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
   }
-  return FMMLM_OK;
+  if (rc == FMMLM_OK) {
+    e = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(plan->gexec, st);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (rc == FMMLM_OK) {
+    plan->gkey = key;
+  } else {
+    drop_graph(plan);
+  }
+  return rc;
 }
 
 int fmm_layered_destroy(fmmlm_plan_t plan) {

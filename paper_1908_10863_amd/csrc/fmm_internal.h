@@ -69,6 +69,23 @@ struct DevBuf {
 
 }  // namespace fmmlm
 
+namespace fmmlm {
+// arguments of the evaluation a plan's captured graph replays
+struct GraphKey {
+  int32_t nrhs = 0;
+  const double* q = nullptr;
+  int64_t ldq = 0;
+  double* phi = nullptr;
+  int64_t ldphi = 0;
+  uint32_t parts = 0;
+  hipStream_t st = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return nrhs == o.nrhs && q == o.q && ldq == o.ldq && phi == o.phi && ldphi == o.ldphi && parts == o.parts &&
+           st == o.st;
+  }
+};
+}  // namespace fmmlm
+
 struct fmmlm_plan_s {
   int L = 0;
   std::vector<double> d, eps;
@@ -110,10 +127,11 @@ struct fmmlm_plan_s {
   double* Tfree = nullptr;         // [nops][nrk][32 mrt] real-form operators (free space, then reaction)
   int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
-  int64_t tile_split = 0;          // tiles [0, tile_split) are on levels kept in FP64
+  int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
   // work units: a tile's steps split into chunks (more blocks in flight)
   int64_t nunits = 0, unit_split = 0;
   int32_t *unit_s = nullptr;       // [2 * nunits] step range of each unit
+  int32_t *unit_mask = nullptr;    // [nunits] column groups of 8 that the unit's partial holds
   int32_t *tile_unit_ptr = nullptr;// [ntiles + 1]
   double* Wm2l = nullptr;          // [nunits][tile_cols][32 mrt] partial products
   // FP32 form
@@ -132,6 +150,7 @@ struct fmmlm_plan_s {
   int64_t ntiles = 0, nsteps = 0;
   int32_t *tile_ptr = nullptr, *tile_tgt = nullptr, *tile_level = nullptr;
   int32_t *step_op = nullptr, *step_src = nullptr, *step_kind = nullptr;
+  int32_t *step_mask = nullptr;    // per step: bit g set if columns [8 g, 8 g + 8) hold a source
   int64_t nops = 0, n_free_ops = 0;
   // P2P free, CSR over leaves
   int32_t *p2p_ptr = nullptr;      // [nleaves + 1]
@@ -150,6 +169,9 @@ struct fmmlm_plan_s {
   double *qt = nullptr, *phit = nullptr;
   double *M = nullptr, *Lx = nullptr;  // [NB][(p+1)^2] real layout
   double *sc_levels = nullptr;     // 1/S_l per level
+  // graph mode: the captured evaluation and its arguments
+  hipGraphExec_t gexec = nullptr;
+  fmmlm::GraphKey gkey;
   // live stage timing
   std::vector<hipEvent_t> prof_ev;  // [max_evals][FMMLM_NSTAGES + 1]
   int prof_cap = 0, prof_used = 0;

@@ -28,7 +28,7 @@ _ERRORS = {
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("fp64_top_levels", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
-                ("mac_d2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("mac_d2", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
                 ("surrogate", ctypes.c_void_p)]
 
 
@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("tree_seconds", ctypes.c_double), ("lists_seconds", ctypes.c_double),
                 ("ops_seconds", ctypes.c_double), ("table_seconds", ctypes.c_double),
                 ("nearfield_seconds", ctypes.c_double), ("surrogate_tasks", ctypes.c_int64),
-                ("surrogate_pairs", ctypes.c_int64), ("surrogate_check", ctypes.c_double)]
+                ("surrogate_pairs", ctypes.c_int64), ("surrogate_check", ctypes.c_double),
+                ("m2l_steps", ctypes.c_int64), ("m2l_tile_cols", ctypes.c_int32),
+                ("reserved_stats", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
@@ -71,7 +73,8 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
            "fmm_layered_surrogate_samples"]
-STAGES = ["gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "p2p_reaction", "combine"]
+STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
+          "combine"]
 
 _lib = None
 
@@ -173,7 +176,7 @@ class Plan:
     """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
 
     def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
-                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None, surrogate=None):
+                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None, surrogate=None, graph=False):
         self.d = _host(d, np.float64)
         self.eps = _host(eps, np.float64)
         x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)
@@ -189,6 +192,7 @@ class Plan:
             o.mac_d2 = mac_d2
         if surrogate is not None:
             o.surrogate = surrogate._h
+        o.graph = 1 if graph else 0
         h = ctypes.c_void_p()
         rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
                                     _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),
