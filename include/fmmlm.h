@@ -181,7 +181,8 @@ typedef struct {
   int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
                                     (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
   int32_t reserved_stats;
-  int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64 (0 otherwise) */
+  int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64, run by the
+                                    "M2L top" stage (0 in the FP64 form) */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
@@ -354,7 +355,8 @@ int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const 
  * P2P reaction, combine).  "M2L" is one kernel launch: the main M2L GEMM (the
  * matrix-core kernel below the FP64 levels in the FP32 form, the FP64 kernel
  * over every level otherwise); "M2L top" clears the local expansions and, in
- * the FP32 form, runs the FP64 levels and converts the multipole expansions.
+ * the FP32 form, runs the FP64 levels (sparse kernel) and converts the
+ * multipole expansions.
  * profile_end synchronises the device, writes the summed milliseconds of each
  * stage over the recorded evaluations to stage_ms[FMMLM_NSTAGES] (host), the
  * number of recorded evaluations to *n_evals, and stops recording.

@@ -650,11 +650,26 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     // height row, since a reaction operator depends on the heights of both
     // boxes above their interfaces.  Inside a bucket, boxes with the same
     // operator set are put next to each other.
-    const int k64 = P->fp32 ? P->opts.fp64_top_levels : P->maxlev + 1;
+    // In the FP32 form the levels kept in FP64 (few boxes, many distinct
+    // operators) run in the sparse FP64 kernel instead of tiles; the FP64 form
+    // tiles every level (its top-level tiles share the one large launch).
+    const int ksp = P->fp32 ? P->opts.fp64_top_levels : 0;
+    const int k64 = P->fp32 ? ksp : P->maxlev + 1;
+    {
+      std::vector<int32_t> spb;
+      for (int l = 0; l < std::min(ksp, P->maxlev + 1); ++l)
+        for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
+          if (mptr[b + 1] > mptr[b]) {
+            spb.push_back((int32_t)b);
+            P->stats.m2l_top_pairs += mptr[b + 1] - mptr[b];
+          }
+      P->n_sp_boxes = (int64_t)spb.size();
+      if (int rc0 = dev_upload(P, &P->sp_boxes, spb, st)) return rc0;
+    }
     P->tile_grp[0] = 0;
     for (int grp = 0; grp < 4; ++grp) {
       const bool reac = (grp & 1) != 0;
-      for (int l = 0; l <= P->maxlev; ++l) {
+      for (int l = ksp; l <= P->maxlev; ++l) {
         if ((l < k64) != (grp < 2)) continue;
         std::vector<std::tuple<uint64_t, uint64_t, int32_t>> key;  // (bucket, operator-set hash, box)
         std::vector<int> ops;
@@ -708,10 +723,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
               ssrc.insert(ssrc.end(), cv.begin(), cv.end());
               uint32_t msk = 0;  // bit g: a source in columns [8 g, 8 g + 8)
               for (int c = 0; c < TBc; ++c)
-                if (cv[c] >= 0) {
-                  msk |= 1u << (c >> 3);
-                  if (P->fp32 && grp < 2) ++P->stats.m2l_top_pairs;
-                }
+                if (cv[c] >= 0) msk |= 1u << (c >> 3);
               smask.push_back((int32_t)msk);
             }
             for (int op : used) slot[op] = -1;

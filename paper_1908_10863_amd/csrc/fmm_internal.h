@@ -128,6 +128,8 @@ struct fmmlm_plan_s {
   int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
   int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
+  int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
+  int64_t n_sp_boxes = 0;
   // work units: a tile's steps split into chunks (more blocks in flight)
   int64_t nunits = 0, unit_split = 0;
   int32_t *unit_s = nullptr;       // [2 * nunits] step range of each unit
