@@ -87,8 +87,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--p", type=int, default=None)
-    ap.add_argument("--leaf-cap", type=int, default=128)
-    ap.add_argument("--leaf-cap-fp64", type=int, default=128)
+    ap.add_argument("--leaf-cap", type=int, default=192)
+    ap.add_argument("--leaf-cap-fp64", type=int, default=192)
     ap.add_argument("--mac", type=int, default=4)
     ap.add_argument("--rhs", type=int, default=1, help="charge vectors per evaluation (batched form)")
     ap.add_argument("--cpu-sample", type=int, default=4096,

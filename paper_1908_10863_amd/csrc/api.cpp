@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <unordered_set>
 #include <cmath>
@@ -762,6 +763,92 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       return FMMLM_ENOMEM;
     }
   }
+  // ---- M2M / L2L as GEMMs over tiles of up to tile_cols target boxes of one
+  // level: M2M tiles hold parents (one step per child octant present, source
+  // = that child, operator = octant); L2L tiles hold children of one octant
+  // (one step, source = the parent, operator 8 + octant).  One unit per step.
+  {
+    const int TBc = P->tile_cols;
+    std::vector<int32_t> xop, xkind, xsrc, xmask, xus, xumask, xtuptr(1, 0), xtgt, xlev;
+    auto add_tile = [&](int l, const std::vector<int32_t>& tg, const std::vector<std::vector<int32_t>>& src,
+                        const std::vector<int>& ops) {
+      xlev.push_back(l);
+      for (int c = 0; c < TBc; ++c) xtgt.push_back(c < (int)tg.size() ? tg[c] : -1);
+      for (size_t k = 0; k < ops.size(); ++k) {
+        const int32_t a = (int32_t)xop.size();
+        xop.push_back(ops[k]);
+        xkind.push_back((int32_t)(FMMLM_FREE | FMMLM_REACTION));
+        uint32_t msk = 0;
+        for (int c = 0; c < TBc; ++c) {
+          const int32_t v = c < (int)src[k].size() ? src[k][c] : -1;
+          xsrc.push_back(v);
+          if (v >= 0) msk |= 1u << (c >> 3);
+        }
+        xmask.push_back((int32_t)msk);
+        xus.push_back(a);
+        xus.push_back(a + 1);
+        xumask.push_back((int32_t)msk);
+      }
+      xtuptr.push_back((int32_t)(xus.size() / 2));
+    };
+    auto octant = [&](int64_t b) {
+      const HBox& bx = B.boxes[b];
+      return (bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2);
+    };
+    P->xl_m2m.assign(P->maxlev + 1, {0, 0, 0, 0});
+    P->xl_l2l.assign(P->maxlev + 1, {0, 0, 0, 0});
+    for (int l = 0; l <= P->maxlev; ++l) {
+      // M2M into the parents of level l
+      std::array<int64_t, 4> r{(int64_t)xlev.size(), (int64_t)(xus.size() / 2), 0, 0};
+      std::vector<int32_t> par;
+      for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
+        if (B.boxes[b].nchild > 0) par.push_back((int32_t)b);
+      for (size_t c0 = 0; c0 < par.size(); c0 += TBc) {
+        std::vector<int32_t> tg(par.begin() + c0, par.begin() + std::min(par.size(), c0 + TBc));
+        std::vector<std::vector<int32_t>> src(8, std::vector<int32_t>(tg.size(), -1));
+        for (size_t c = 0; c < tg.size(); ++c) {
+          const HBox& bx = B.boxes[tg[c]];
+          for (int k = 0; k < bx.nchild; ++k) src[octant(bx.child0 + k)][c] = bx.child0 + k;
+        }
+        std::vector<int> ops;
+        std::vector<std::vector<int32_t>> used;
+        for (int o = 0; o < 8; ++o)
+          if (std::any_of(src[o].begin(), src[o].end(), [](int32_t v) { return v >= 0; })) {
+            ops.push_back(o);
+            used.push_back(src[o]);
+          }
+        add_tile(l, tg, used, ops);
+      }
+      r[2] = (int64_t)xlev.size();
+      r[3] = (int64_t)(xus.size() / 2);
+      P->xl_m2m[l] = r;
+      // L2L into the children of level l
+      std::array<int64_t, 4> q{(int64_t)xlev.size(), (int64_t)(xus.size() / 2), 0, 0};
+      if (l >= 1) {
+        for (int o = 0; o < 8; ++o) {
+          std::vector<int32_t> ch;
+          for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
+            if (octant(b) == o) ch.push_back((int32_t)b);
+          for (size_t c0 = 0; c0 < ch.size(); c0 += TBc) {
+            std::vector<int32_t> tg(ch.begin() + c0, ch.begin() + std::min(ch.size(), c0 + TBc));
+            std::vector<std::vector<int32_t>> src(1, std::vector<int32_t>(tg.size()));
+            for (size_t c = 0; c < tg.size(); ++c) src[0][c] = B.boxes[tg[c]].parent;
+            add_tile(l, tg, src, {8 + o});
+          }
+        }
+      }
+      q[2] = (int64_t)xlev.size();
+      q[3] = (int64_t)(xus.size() / 2);
+      P->xl_l2l[l] = q;
+    }
+    P->xl_units = (int64_t)(xus.size() / 2);
+    int rc0;
+#define UPX(field, vec) if ((rc0 = dev_upload(P, &P->field, vec, st))) return rc0
+    UPX(xl_step_op, xop); UPX(xl_step_kind, xkind); UPX(xl_step_src, xsrc); UPX(xl_step_mask, xmask);
+    UPX(xl_unit_s, xus); UPX(xl_unit_mask, xumask); UPX(xl_tile_unit_ptr, xtuptr); UPX(xl_tile_tgt, xtgt);
+#undef UPX
+    if ((rc0 = dev_alloc(P, &P->Wxl, (size_t)std::max<int64_t>(P->xl_units, 1) * TBc * 32 * P->mrt))) return rc0;
+  }
   // ---- P2P CSR over leaves
   std::vector<int32_t> pptr(P->nleaves + 1, 0), psrc;
   std::vector<int32_t> rptr(P->nleaves + 1, 0), rsrc;
@@ -869,6 +956,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (rc) return rc;
   if ((rc = dev_alloc(P, &P->Tfree, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;
   if ((rc = gpu_build_real_ops(P, st))) return rc;
+  if ((rc = dev_alloc(P, &P->Txl, (size_t)16 * P->nrk * 32 * P->mrt))) return rc;
+  if ((rc = gpu_build_xlate_ops(P, st))) return rc;
   if (P->fp32) {
     const size_t nr = (size_t)(P->p + 1) * (P->p + 1);
     if ((rc = dev_alloc(P, &P->Tfree32, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/fmmlm.h"
@@ -128,6 +129,14 @@ struct fmmlm_plan_s {
   int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
   int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
+  // M2M / L2L as GEMMs: 16 real-form operators (8 child octants up, 8 down)
+  // and their own tiles; per level (first tile, first unit, end tile, end unit)
+  double* Txl = nullptr;           // [16][nrk][32 mrt]
+  std::vector<std::array<int64_t, 4>> xl_m2m, xl_l2l;
+  int64_t xl_units = 0;
+  int32_t *xl_step_op = nullptr, *xl_step_kind = nullptr, *xl_step_src = nullptr, *xl_step_mask = nullptr;
+  int32_t *xl_unit_s = nullptr, *xl_unit_mask = nullptr, *xl_tile_unit_ptr = nullptr, *xl_tile_tgt = nullptr;
+  double* Wxl = nullptr;           // [xl_units][tile_cols][32 mrt] partial products
   int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
   int64_t n_sp_boxes = 0;
   // work units: a tile's steps split into chunks (more blocks in flight)
@@ -260,6 +269,7 @@ int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
                   const std::vector<int>& reac_task, const std::vector<double>& reac_phi,
                   const std::vector<double>& reac_S, const double* d_tables, hipStream_t st);
 int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
+int gpu_build_xlate_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
 int gpu_eval_batch(fmmlm_plan_s* P, int g, const double* q, int64_t ldq, double* phi, int64_t ldphi,
                    uint32_t parts, hipStream_t st, hipEvent_t* ev);
