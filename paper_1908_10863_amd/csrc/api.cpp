@@ -925,7 +925,26 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(bparent, bparent); UP(bchild0, bchild0); UP(bnchild, bnchild); UP(leaves, leaves);
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
   UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(pl_leaves, plv); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
-  UP(coefA, coefA); UP(sc_levels, scl);
+  // recurrence coefficients of the regular solid harmonics (P2M, L2P):
+  // [cidx(n,m)] a = sqrt((4n^2-1)/(n^2-m^2)), [nc + cidx] b = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)),
+  // [2 nc + m] sqrt((2m+1)/(2m)) (m >= 1), [2 nc + p + 1 + m] sqrt(2m+3)
+  std::vector<double> coefR(2 * ncoef(p) + 2 * (p + 1), 0.0);
+  {
+    const int ncp = ncoef(p);
+    for (int n = 0; n <= p; ++n)
+      for (int m = 0; m <= n; ++m) {
+        if (n >= m + 2) {
+          coefR[cidx(n, m)] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+          coefR[ncp + cidx(n, m)] =
+              std::sqrt(((double)(n - 1) * (n - 1) - (double)m * m) / (4.0 * (n - 1) * (n - 1) - 1.0));
+        }
+      }
+    for (int m = 0; m <= p; ++m) {
+      coefR[2 * ncp + m] = m > 0 ? std::sqrt((2.0 * m + 1.0) / (2.0 * m)) : 1.0;
+      coefR[2 * ncp + p + 1 + m] = std::sqrt(2.0 * m + 3.0);
+    }
+  }
+  UP(coefA, coefA); UP(coefR, coefR); UP(sc_levels, scl);
   UP(tile_ptr, tptr); UP(tile_tgt, ttgt); UP(tile_level, tlev); UP(step_op, sop); UP(step_src, ssrc);
   UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind); UP(step_mask, smask); UP(unit_mask, umask);
   if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) return rc;

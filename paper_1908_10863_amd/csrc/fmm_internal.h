@@ -175,6 +175,7 @@ struct fmmlm_plan_s {
   double *rp_val = nullptr;        // kernel values, row-major per entry (targets x sources)
   // constants
   double *coefA = nullptr;         // A_n^m for n <= 2p, m <= n : [cidx]
+  double *coefR = nullptr;         // solid-harmonic recurrence coefficients for n <= p (P2M, L2P)
   double *coefC2inv = nullptr;     // 1 / c_n^2, n <= p
   // workspace
   double *qt = nullptr, *phit = nullptr;
