@@ -180,9 +180,13 @@ typedef struct {
   int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one tile) ... */
   int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
                                     (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
-  int32_t reserved_stats;
+  int32_t m2l_variant;         /* FP32 form: M2L tile shape picked by the plan's autotuner */
   int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64, run by the
                                     "M2L top" stage (0 in the FP64 form) */
+  double m2l_variant_ms[6];    /* autotuner: time of one M2L launch in each tile shape (outputs per
+                                  wave, rows x columns; 0: 4 waves of 64 x 64, 1: 8 of 32 x 64,
+                                  2: 8 of 64 x 32, 3: 16 of 32 x 32, 4: 16 of 64 x 16, 5: 16 of
+                                  16 x 64; (p+1)^2 <= 128 only, else unused) */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);

@@ -1027,6 +1027,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
   if (P->fp32 && G > 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nrr * G))) return rc;
+  if (P->fp32 && (rc = gpu_tune_m2l(P, st))) return rc;
   if (G > 1) {
     if ((rc = dev_alloc(P, &P->qb64, P->NP * 64))) return rc;
     if (P->fp32 && (rc = dev_alloc(P, &P->qb32, P->NP * 64))) return rc;

@@ -129,6 +129,7 @@ struct fmmlm_plan_s {
   int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
   int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
+  int m2l_variant = 0;             // FP32 M2L tile shape picked by the autotuner
   // M2M / L2L as GEMMs: 16 real-form operators (8 child octants up, 8 down)
   // and their own tiles; per level (first tile, first unit, end tile, end unit)
   double* Txl = nullptr;           // [16][nrk][32 mrt]
@@ -271,6 +272,8 @@ int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
                   const std::vector<double>& reac_S, const double* d_tables, hipStream_t st);
 int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_xlate_ops(fmmlm_plan_s* P, hipStream_t st);
+int gpu_tune_m2l(fmmlm_plan_s* P, hipStream_t st);
+constexpr int kM2LVariants = 6;  // FP32 M2L tile shapes the autotuner tries
 int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
 int gpu_eval_batch(fmmlm_plan_s* P, int g, const double* q, int64_t ldq, double* phi, int64_t ldphi,
                    uint32_t parts, hipStream_t st, hipEvent_t* ev);

@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("nearfield_seconds", ctypes.c_double), ("surrogate_tasks", ctypes.c_int64),
                 ("surrogate_pairs", ctypes.c_int64), ("surrogate_check", ctypes.c_double),
                 ("m2l_steps", ctypes.c_int64), ("m2l_tile_cols", ctypes.c_int32),
-                ("reserved_stats", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64)]
+                ("m2l_variant", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64),
+                ("m2l_variant_ms", ctypes.c_double * 6)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
@@ -220,7 +221,9 @@ class Plan:
     def stats(self) -> dict:
         s = Stats()
         check(lib().fmm_layered_plan_stats(self._h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        out = {f: getattr(s, f) for f, _ in Stats._fields_}
+        out["m2l_variant_ms"] = list(out["m2l_variant_ms"])
+        return out
 
     def tree(self, t):
         lay = ctypes.c_int32()
