@@ -187,9 +187,23 @@ typedef struct {
                                   wave, rows x columns; 0: 4 waves of 64 x 64, 1: 8 of 32 x 64,
                                   2: 8 of 64 x 32, 3: 16 of 32 x 32, 4: 16 of 64 x 16, 5: 16 of
                                   16 x 64; (p+1)^2 <= 128 only, else unused) */
+  int32_t batch_variant;       /* batched FP32 form: M2L variant picked by the autotuner ... */
+  int32_t reserved_stats2;
+  double batch_variant_ms[10]; /*   ... and one launch's time in each: variant v has the tile shape
+                                  v % 5 (outputs per wave over operator rows x 64 vectors; 0: 4 waves
+                                  of 64 x 32, 1: 8 of 32 x 32, 2: 8 of 64 x 16, 3: 16 of 32 x 16,
+                                  4: 16 of 16 x 32) as one block per target box (v < 5) or as a
+                                  persistent XCD-aware grid (v >= 5); (p+1)^2 <= 128 only */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
+
+/* Overrides the autotuner's choices (tests, benchmarks): m2l_variant selects the
+ * FP32 M2L tile shape (0..5, see m2l_variant_ms), batch_variant the batched FP32
+ * M2L variant (0..9, see batch_variant_ms); -1 leaves a choice unchanged.
+ * FMMLM_EINVAL for a value out of range or a variant the plan does not have
+ * ((p+1)^2 > 128 has one shape: 0, or 0 and 1 for the batched M2L). */
+int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant);
 
 /*
  * Tree t (0 <= t < n_trees) of a plan.  Trees are ordered by layer, then side

@@ -293,6 +293,10 @@ void drop_graph(fmmlm_plan_s* P) {
 
 void free_plan(fmmlm_plan_s* P) {
   drop_graph(P);
+  for (hipEvent_t e : {P->ev_q, P->ev_m, P->ev_near, P->ev_top})
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t q : {P->s_near, P->s_top})
+    if (q) (void)hipStreamDestroy(q);
   if (!P) return;
   for (auto e : P->prof_ev) (void)hipEventDestroy(e);
   for (auto& b : P->bufs) hipFree(b.ptr);
@@ -1024,6 +1028,11 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   const size_t nrr = (size_t)(P->p + 1) * (P->p + 1);
   if ((rc = dev_alloc(P, &P->qt, P->NP * G))) return rc;
   if ((rc = dev_alloc(P, &P->phit, P->NP * G))) return rc;
+  if ((rc = dev_alloc(P, &P->phin, P->NP))) return rc;
+  FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_near, hipStreamNonBlocking));
+  FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_top, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&P->ev_q, &P->ev_m, &P->ev_near, &P->ev_top})
+    FMM_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
   if (P->fp32 && G > 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nrr * G))) return rc;
@@ -1039,6 +1048,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       }
     P->nbbox = (int64_t)bb.size();
     if ((rc = dev_upload(P, &P->bbox, bb, st))) return rc;
+    if (P->fp32 && (rc = gpu_tune_batch(P, st))) return rc;
   }
   FMM_HIP_TRY(hipStreamSynchronize(st));
   return FMMLM_OK;
@@ -1336,6 +1346,17 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
     drop_graph(plan);
   }
   return rc;
+}
+
+int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant) {
+  if (!plan) return FMMLM_EINVAL;
+  const int nm = plan->mrt == 4 ? kM2LVariants : 1;
+  const int nb = plan->mrt == 4 ? 2 * kBatchShapes : 2;
+  if (m2l_variant < -1 || m2l_variant >= nm || batch_variant < -1 || batch_variant >= nb) return FMMLM_EINVAL;
+  if (m2l_variant >= 0) plan->m2l_variant = plan->stats.m2l_variant = m2l_variant;
+  if (batch_variant >= 0) plan->batch_variant = plan->stats.batch_variant = batch_variant;
+  drop_graph(plan);  // a captured evaluation holds the old launches
+  return FMMLM_OK;
 }
 
 int fmm_layered_destroy(fmmlm_plan_t plan) {

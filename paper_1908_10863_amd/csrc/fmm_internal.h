@@ -130,6 +130,7 @@ struct fmmlm_plan_s {
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
   int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
   int m2l_variant = 0;             // FP32 M2L tile shape picked by the autotuner
+  int batch_variant = 0;           // batched FP32 M2L shape / persistence picked by the autotuner
   // M2M / L2L as GEMMs: 16 real-form operators (8 child octants up, 8 down)
   // and their own tiles; per level (first tile, first unit, end tile, end unit)
   double* Txl = nullptr;           // [16][nrk][32 mrt]
@@ -182,6 +183,11 @@ struct fmmlm_plan_s {
   double *qt = nullptr, *phit = nullptr;
   double *M = nullptr, *Lx = nullptr;  // [NB][(p+1)^2] real layout
   double *sc_levels = nullptr;     // 1/S_l per level
+  // single-vector evaluations: the near field (into phin) and the sparse top
+  // levels run on their own streams, joined to the caller's stream by events
+  double* phin = nullptr;          // near-field potentials, tree order [NP]
+  hipStream_t s_near = nullptr, s_top = nullptr;
+  hipEvent_t ev_q = nullptr, ev_m = nullptr, ev_near = nullptr, ev_top = nullptr;
   // graph mode: the captured evaluation and its arguments
   hipGraphExec_t gexec = nullptr;
   fmmlm::GraphKey gkey;
@@ -274,6 +280,8 @@ int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_xlate_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_tune_m2l(fmmlm_plan_s* P, hipStream_t st);
 constexpr int kM2LVariants = 6;  // FP32 M2L tile shapes the autotuner tries
+constexpr int kBatchShapes = 5;  // batched FP32 M2L tile shapes (each also persistent)
+int gpu_tune_batch(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
 int gpu_eval_batch(fmmlm_plan_s* P, int g, const double* q, int64_t ldq, double* phi, int64_t ldphi,
                    uint32_t parts, hipStream_t st, hipEvent_t* ev);

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("surrogate_pairs", ctypes.c_int64), ("surrogate_check", ctypes.c_double),
                 ("m2l_steps", ctypes.c_int64), ("m2l_tile_cols", ctypes.c_int32),
                 ("m2l_variant", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64),
-                ("m2l_variant_ms", ctypes.c_double * 6)]
+                ("m2l_variant_ms", ctypes.c_double * 6), ("batch_variant", ctypes.c_int32),
+                ("reserved_stats2", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
@@ -73,7 +74,7 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_create_for_plan", "fmm_layered_surrogate_train",
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
-           "fmm_layered_surrogate_samples"]
+           "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -144,6 +145,8 @@ def lib():
     L.fmm_layered_surrogate_eval.restype = ctypes.c_int
     L.fmm_layered_surrogate_samples.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp]
     L.fmm_layered_surrogate_samples.restype = ctypes.c_int
+    L.fmm_layered_plan_set_variants.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.fmm_layered_plan_set_variants.restype = ctypes.c_int
     L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
     L.fmm_layered_profile_begin.restype = ctypes.c_int
     L.fmm_layered_profile_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -218,11 +221,16 @@ class Plan:
         check(rc)
         return out.reshape(q.shape)
 
+    def set_variants(self, m2l=-1, batch=-1):
+        """Override the autotuner's kernel variants (see fmm_layered_plan_set_variants)."""
+        check(lib().fmm_layered_plan_set_variants(self._h, m2l, batch))
+
     def stats(self) -> dict:
         s = Stats()
         check(lib().fmm_layered_plan_stats(self._h, ctypes.byref(s)))
         out = {f: getattr(s, f) for f, _ in Stats._fields_}
         out["m2l_variant_ms"] = list(out["m2l_variant_ms"])
+        out["batch_variant_ms"] = list(out["batch_variant_ms"])
         return out
 
     def tree(self, t):
