@@ -767,12 +767,13 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       return FMMLM_ENOMEM;
     }
   }
-  // ---- M2M / L2L as GEMMs over tiles of up to tile_cols target boxes of one
+  // ---- M2M / L2L as GEMMs over tiles of up to xl_tile_cols target boxes of one
   // level: M2M tiles hold parents (one step per child octant present, source
   // = that child, operator = octant); L2L tiles hold children of one octant
   // (one step, source = the parent, operator 8 + octant).  One unit per step.
   {
-    const int TBc = P->tile_cols;
+    // narrow tiles: a level's translations are few, so more and smaller blocks
+    const int TBc = P->xl_tile_cols;
     std::vector<int32_t> xop, xkind, xsrc, xmask, xus, xumask, xtuptr(1, 0), xtgt, xlev;
     auto add_tile = [&](int l, const std::vector<int32_t>& tg, const std::vector<std::vector<int32_t>>& src,
                         const std::vector<int>& ops) {

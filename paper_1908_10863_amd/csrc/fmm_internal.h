@@ -138,7 +138,8 @@ struct fmmlm_plan_s {
   int64_t xl_units = 0;
   int32_t *xl_step_op = nullptr, *xl_step_kind = nullptr, *xl_step_src = nullptr, *xl_step_mask = nullptr;
   int32_t *xl_unit_s = nullptr, *xl_unit_mask = nullptr, *xl_tile_unit_ptr = nullptr, *xl_tile_tgt = nullptr;
-  double* Wxl = nullptr;           // [xl_units][tile_cols][32 mrt] partial products
+  double* Wxl = nullptr;           // [xl_units][xl_tile_cols][32 mrt] partial products
+  int xl_tile_cols = 32;           // target boxes per translation tile
   int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
   int64_t n_sp_boxes = 0;
   // work units: a tile's steps split into chunks (more blocks in flight)
