@@ -1049,6 +1049,42 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       }
     P->nbbox = (int64_t)bb.size();
     if ((rc = dev_upload(P, &P->bbox, bb, st))) return rc;
+    {
+      auto octant = [&](int64_t b) {
+        const HBox& bx = B.boxes[b];
+        return (bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2);
+      };
+      std::vector<int32_t> uptr(P->NB + 1, 0), usrc, uop, ub, dptr(P->NB + 1, 0), dsrc, dop, db;
+      P->bu_lev.assign(1, 0);
+      P->bd_lev.assign(1, 0);
+      for (int l = 0; l <= P->maxlev; ++l) {
+        for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b) {
+          const HBox& bx = B.boxes[b];
+          if (bx.nchild > 0) ub.push_back((int32_t)b);
+          if (l >= 1) db.push_back((int32_t)b);
+        }
+        P->bu_lev.push_back((int64_t)ub.size());
+        P->bd_lev.push_back((int64_t)db.size());
+      }
+      for (int64_t b = 0; b < P->NB; ++b) {
+        const HBox& bx = B.boxes[b];
+        for (int k = 0; k < bx.nchild; ++k) {
+          usrc.push_back(bx.child0 + k);
+          uop.push_back(octant(bx.child0 + k));
+        }
+        uptr[b + 1] = (int32_t)usrc.size();
+        if (bx.level >= 1) {
+          dsrc.push_back(bx.parent);
+          dop.push_back(8 + octant(b));
+        }
+        dptr[b + 1] = (int32_t)dsrc.size();
+      }
+      if ((rc = dev_upload(P, &P->bu_ptr, uptr, st)) || (rc = dev_upload(P, &P->bu_src, usrc, st)) ||
+          (rc = dev_upload(P, &P->bu_op, uop, st)) || (rc = dev_upload(P, &P->bu_boxes, ub, st)) ||
+          (rc = dev_upload(P, &P->bd_ptr, dptr, st)) || (rc = dev_upload(P, &P->bd_src, dsrc, st)) ||
+          (rc = dev_upload(P, &P->bd_op, dop, st)) || (rc = dev_upload(P, &P->bd_boxes, db, st)))
+        return rc;
+    }
     if (P->fp32 && (rc = gpu_tune_batch(P, st))) return rc;
   }
   FMM_HIP_TRY(hipStreamSynchronize(st));

@@ -159,6 +159,12 @@ struct fmmlm_plan_s {
   int gmax = 1;
   int64_t nbbox = 0, bbox_split = 0;
   int32_t* bbox = nullptr;         // target boxes with M2L entries, level order
+  // batched M2M / L2L through the batched FP64 GEMM: per box CSR of its
+  // translation entries (M2M: children, operator = octant; L2L: the parent,
+  // operator 8 + octant) and the target boxes of each level
+  int32_t *bu_ptr = nullptr, *bu_src = nullptr, *bu_op = nullptr, *bu_boxes = nullptr;
+  int32_t *bd_ptr = nullptr, *bd_src = nullptr, *bd_op = nullptr, *bd_boxes = nullptr;
+  std::vector<int64_t> bu_lev, bd_lev;  // level l's targets: [lev[l], lev[l + 1])
   double* qb64 = nullptr;          // [NP][64] vector-minor charges (FP64)
   float* qb32 = nullptr;           // [NP][64] (FP32 form)
   int64_t ntiles = 0, nsteps = 0;
