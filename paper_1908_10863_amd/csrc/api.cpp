@@ -676,6 +676,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       const bool reac = (grp & 1) != 0;
       for (int l = ksp; l <= P->maxlev; ++l) {
         if ((l < k64) != (grp < 2)) continue;
+        if (P->fp32) continue;  // the FP32 form runs these levels operator-major (below)
         std::vector<std::tuple<uint64_t, uint64_t, int32_t>> key;  // (bucket, operator-set hash, box)
         std::vector<int> ops;
         for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b) {
@@ -737,6 +738,59 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
         }
       }
       P->tile_grp[grp + 1] = (int64_t)tlev.size();
+    }
+    // FP32 form, levels below the FP64 ones: operator-major chunks.  All pairs
+    // of one operator (in box units a free-space operator serves every level)
+    // are taken TBc at a time as one step (a tile of its own, one unit); a
+    // target appears at most once per operator, so a chunk's columns are
+    // distinct targets.  Each target's outputs are then summed over its slots
+    // (unit, column) in operator order by m2l_slot_reduce_kernel.
+    if (P->fp32) {
+      std::vector<std::array<int32_t, 3>> pr;  // (operator, target, source)
+      for (int l = ksp; l <= P->maxlev; ++l)
+        for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
+          for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e)
+            pr.push_back({(mop[e] >= 0) ? mop[e] : ~mop[e], (int32_t)b, msrc[e]});
+      std::sort(pr.begin(), pr.end());
+      std::vector<std::vector<int32_t>> tslots(P->NB);
+      for (size_t i0 = 0; i0 < pr.size();) {
+        size_t i1 = i0;
+        while (i1 < pr.size() && pr[i1][0] == pr[i0][0]) ++i1;
+        const int op = pr[i0][0];
+        for (size_t c0 = i0; c0 < i1; c0 += TBc) {
+          const size_t nc_ = std::min<size_t>(TBc, i1 - c0);
+          const int32_t unit = (int32_t)tlev.size();  // one unit per chunk
+          tlev.push_back(B.boxes[pr[c0][1]].level);
+          uint32_t msk = 0;
+          for (size_t c = 0; c < (size_t)TBc; ++c) {
+            const bool on = c < nc_;
+            ttgt.push_back(on ? pr[c0 + c][1] : -1);
+            ssrc.push_back(on ? pr[c0 + c][2] : -1);
+            if (on) {
+              msk |= 1u << (c >> 3);
+              tslots[pr[c0 + c][1]].push_back(unit * TBc + (int32_t)c);
+            }
+          }
+          sop.push_back(op);
+          skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
+          smask.push_back((int32_t)msk);
+          tptr.push_back((int32_t)sop.size());
+        }
+        i0 = i1;
+      }
+      P->tile_grp[3] = P->tile_grp[4] = (int64_t)tlev.size();
+      std::vector<int32_t> sbox, sptr(1, 0), slots;
+      for (int64_t b = 0; b < P->NB; ++b)
+        if (!tslots[b].empty()) {
+          sbox.push_back((int32_t)b);
+          slots.insert(slots.end(), tslots[b].begin(), tslots[b].end());
+          sptr.push_back((int32_t)slots.size());
+        }
+      P->n_slot_boxes = (int64_t)sbox.size();
+      int rc0;
+      if ((rc0 = dev_upload(P, &P->slot_boxes, sbox, st)) || (rc0 = dev_upload(P, &P->slot_ptr, sptr, st)) ||
+          (rc0 = dev_upload(P, &P->slots, slots, st)))
+        return rc0;
     }
     P->ntiles = (int64_t)tlev.size();
     P->nsteps = (int64_t)sop.size();
@@ -952,7 +1006,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(coefA, coefA); UP(coefR, coefR); UP(sc_levels, scl);
   UP(tile_ptr, tptr); UP(tile_tgt, ttgt); UP(tile_level, tlev); UP(step_op, sop); UP(step_src, ssrc);
   UP(unit_s, us); UP(tile_unit_ptr, tuptr); UP(step_kind, skind); UP(step_mask, smask); UP(unit_mask, umask);
-  if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) return rc;
+  if (P->fp32) {
+    if ((rc = dev_alloc(P, &P->W32m, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt)))
+      return rc;
+  } else if ((rc = dev_alloc(P, &P->Wm2l, (size_t)std::max<int64_t>(P->nunits, 1) * P->tile_cols * 32 * P->mrt))) {
+    return rc;
+  }
 #undef UP
   P->stats.lists_seconds = seconds_since(tphase);
   tphase = std::chrono::steady_clock::now();

@@ -141,13 +141,17 @@ struct fmmlm_plan_s {
   double* Wxl = nullptr;           // [xl_units][xl_tile_cols][32 mrt] partial products
   int xl_tile_cols = 32;           // target boxes per translation tile
   int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
+  // FP32 form: operator-major chunks; per target box its slots (unit * tile_cols + column)
+  int32_t *slot_boxes = nullptr, *slot_ptr = nullptr, *slots = nullptr;
+  int64_t n_slot_boxes = 0;
   int64_t n_sp_boxes = 0;
   // work units: a tile's steps split into chunks (more blocks in flight)
   int64_t nunits = 0, unit_split = 0;
   int32_t *unit_s = nullptr;       // [2 * nunits] step range of each unit
   int32_t *unit_mask = nullptr;    // [nunits] column groups of 8 that the unit's partial holds
   int32_t *tile_unit_ptr = nullptr;// [ntiles + 1]
-  double* Wm2l = nullptr;          // [nunits][tile_cols][32 mrt] partial products
+  double* Wm2l = nullptr;          // [nunits][tile_cols][32 mrt] partial products (FP64 form)
+  float* W32m = nullptr;           // the same in FP32 (FP32 form: single-step units)
   // FP32 form
   bool fp32 = false;
   float* Tfree32 = nullptr;        // FP32 copy of Tfree
