@@ -670,6 +670,25 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
           }
       P->n_sp_boxes = (int64_t)spb.size();
       if (int rc0 = dev_upload(P, &P->sp_boxes, spb, st)) return rc0;
+      // work items: runs of kSpItemRounds rounds of sp_ne entries (the block's
+      // threads hold sp_ne entries x nc coefficients; LDS holds their source
+      // expansions, operator tables and sums, at most 60 KiB)
+      const int nc = P->nc, ng = P->ng, nr = (P->p + 1) * (P->p + 1);
+      P->sp_ne = std::max(1, std::min(kSpThreads / nc, 61440 / ((nr + ng + nc) * 16)));
+      const int run = kSpItemRounds * P->sp_ne;
+      std::vector<int32_t> items, iptr(1, 0);
+      for (const int32_t b : spb) {
+        for (int32_t e = mptr[b]; e < mptr[b + 1]; e += run) {
+          items.push_back(b);
+          items.push_back(e);
+          items.push_back(std::min<int32_t>(e + run, mptr[b + 1]));
+        }
+        iptr.push_back((int32_t)(items.size() / 3));
+      }
+      P->n_sp_items = (int64_t)(items.size() / 3);
+      if (int rc0 = dev_upload(P, &P->sp_items, items, st)) return rc0;
+      if (int rc0 = dev_upload(P, &P->sp_item_ptr, iptr, st)) return rc0;
+      if (int rc0 = dev_alloc(P, &P->Psp, (size_t)std::max<int64_t>(P->n_sp_items, 1) * nc * 2)) return rc0;
     }
     P->tile_grp[0] = 0;
     for (int grp = 0; grp < 4; ++grp) {
@@ -913,7 +932,10 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   std::vector<int32_t> rptr(P->nleaves + 1, 0), rsrc;
   std::vector<int64_t> rvoff;
   std::vector<int32_t> rp_t, rp_s, rp_c;
-  int64_t voff = 0;
+  // reaction rows: entry e's target rows have partial sums at rrow[e] + i;
+  // work units of kRPUnitRows rows (entry, first row, target count)
+  std::vector<int32_t> rrow, runits;
+  int64_t voff = 0, nrows = 0;
   for (int64_t li = 0; li < P->nleaves; ++li) {
     const int b = leaves[li];
     for (auto& pr : B.p2p_free[b]) {
@@ -922,6 +944,14 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     pptr[li + 1] = (int32_t)(psrc.size() / 2);
     for (auto& r : B.p2p_reac[b]) {
+      const int32_t tcnt = (int32_t)B.boxes[b].count;
+      for (int32_t r0 = 0; r0 < tcnt; r0 += kRPUnitRows) {
+        runits.push_back((int32_t)rvoff.size());
+        runits.push_back(r0);
+        runits.push_back(tcnt);
+      }
+      rrow.push_back((int32_t)nrows);
+      nrows += tcnt;
       rsrc.push_back(r.start);
       rsrc.push_back(r.count);
       rvoff.push_back(voff);
@@ -984,6 +1014,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(bparent, bparent); UP(bchild0, bchild0); UP(bnchild, bnchild); UP(leaves, leaves);
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
   UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(pl_leaves, plv); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
+  UP(rp_row, rrow); UP(rp_units, runits);
+  P->n_rp_units = (int64_t)(runits.size() / 3);
+  if ((rc = dev_alloc(P, &P->Prp, (size_t)std::max<int64_t>(nrows, 1)))) return rc;
   // recurrence coefficients of the regular solid harmonics (P2M, L2P):
   // [cidx(n,m)] a = sqrt((4n^2-1)/(n^2-m^2)), [nc + cidx] b = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)),
   // [2 nc + m] sqrt((2m+1)/(2m)) (m >= 1), [2 nc + p + 1 + m] sqrt(2m+3)

@@ -15,6 +15,11 @@ namespace fmmlm {
 constexpr int kMaxL = FMMLM_MAX_INTERFACES;
 constexpr int kPMax = FMMLM_PMAX;
 constexpr int kMaxLevel = 20;  // 21-bit quantisation per axis
+// sparse top-level M2L: threads of a block, rounds of entries per work item
+constexpr int kSpThreads = 512;
+constexpr int kSpItemRounds = 4;
+// reaction P2P: target rows per work unit (one wave, 8 lanes a row)
+constexpr int kRPUnitRows = 8;
 
 // ---- small complex type (device and host) ------------------------------------
 struct cplx {
@@ -141,6 +146,12 @@ struct fmmlm_plan_s {
   double* Wxl = nullptr;           // [xl_units][xl_tile_cols][32 mrt] partial products
   int xl_tile_cols = 32;           // target boxes per translation tile
   int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
+  // their work items (sparse box, first entry, end entry), per box a run of
+  // items (sp_item_ptr), partial sums per item [n_sp_items][nc] complex
+  int32_t *sp_items = nullptr, *sp_item_ptr = nullptr;
+  int64_t n_sp_items = 0;
+  int sp_ne = 1;                   // entries per round of an item's block
+  double* Psp = nullptr;
   // FP32 form: operator-major chunks; per target box its slots (unit * tile_cols + column)
   int32_t *slot_boxes = nullptr, *slot_ptr = nullptr, *slots = nullptr;
   int64_t n_slot_boxes = 0;
@@ -186,6 +197,10 @@ struct fmmlm_plan_s {
   int32_t *rp_src = nullptr;       // [2 * entries] (start, count)
   int64_t *rp_voff = nullptr;      // [entries] value offset
   double *rp_val = nullptr;        // kernel values, row-major per entry (targets x sources)
+  int32_t *rp_row = nullptr;       // [entries] first partial-sum slot of the entry's target rows
+  int32_t *rp_units = nullptr;     // [3 * n_rp_units] (entry, first row, target count)
+  int64_t n_rp_units = 0;
+  double *Prp = nullptr;           // per (entry, target row) partial sums
   // constants
   double *coefA = nullptr;         // A_n^m for n <= 2p, m <= n : [cidx]
   double *coefR = nullptr;         // solid-harmonic recurrence coefficients for n <= p (P2M, L2P)
