@@ -833,6 +833,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     if (P->ntiles == P->tile_grp[2]) P->unit_split = (int64_t)(us.size() / 2);
     P->nunits = (int64_t)(us.size() / 2);
+    // the FP32 matrix-core kernel takes one-step units only
+    for (int64_t u = P->unit_split; P->fp32 && u < P->nunits; ++u)
+      if (us[2 * u + 1] - us[2 * u] != 1) {
+        set_last_error("internal: FP32 M2L unit with more than one step");
+        return FMMLM_EUNSUPPORTED;
+      }
     // operator tables must fit a budget (FP64 + FP32 copies)
     const double tbytes = (double)P->nops * P->nrk * 32.0 * P->mrt * (P->fp32 ? 12.0 : 8.0);
     if (tbytes > 32.0 * (1 << 30)) {
