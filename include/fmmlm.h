@@ -180,13 +180,15 @@ typedef struct {
   int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one tile) ... */
   int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
                                     (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
-  int32_t m2l_variant;         /* FP32 form: M2L tile shape picked by the plan's autotuner */
+  int32_t m2l_variant;         /* FP32 form: M2L tile shape picked by the plan's autotuner (see m2l_eval_ms) */
   int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64, run by the
                                     "M2L top" stage (0 in the FP64 form) */
-  double m2l_variant_ms[6];    /* autotuner: time of one M2L launch in each tile shape (outputs per
-                                  wave, rows x columns; 0: 4 waves of 64 x 64, 1: 8 of 32 x 64,
-                                  2: 8 of 64 x 32, 3: 16 of 32 x 32, 4: 16 of 64 x 16, 5: 16 of
-                                  16 x 64; (p+1)^2 <= 128 only, else unused) */
+  double m2l_variant_ms[6];    /* autotuner: time of one M2L launch alone in each tile shape (outputs
+                                  per wave, rows x columns, operator columns per LDS slice; 0: 16
+                                  waves of 32 x 32, slices of 32; 1: 8 of 32 x 64; 2: 8 of 64 x 32;
+                                  3: 16 of 32 x 32; 4: 16 of 64 x 16; 5: 16 of 64 x 16, slices of
+                                  32; slices of 16 otherwise, and where the padded column count is
+                                  not a multiple of 32; (p+1)^2 <= 128 only, else unused) */
   int32_t batch_variant;       /* batched FP32 form: M2L variant picked by the autotuner ... */
   int32_t reserved_stats2;
   double batch_variant_ms[10]; /*   ... and one launch's time in each: variant v has the tile shape
@@ -194,6 +196,9 @@ typedef struct {
                                   of 64 x 32, 1: 8 of 32 x 32, 2: 8 of 64 x 16, 3: 16 of 32 x 16,
                                   4: 16 of 16 x 32) as one block per target box (v < 5) or as a
                                   persistent XCD-aware grid (v >= 5); (p+1)^2 <= 128 only */
+  double m2l_eval_ms[6];       /* FP32 form: time of a whole unprofiled evaluation (near field and
+                                  sparse top levels on their streams beside the main M2L) with
+                                  each tile shape; m2l_variant is the fastest of these */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);

@@ -1186,6 +1186,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     if (P->fp32 && (rc = gpu_tune_batch(P, st))) return rc;
   }
   FMM_HIP_TRY(hipStreamSynchronize(st));
+  if (P->fp32 && (rc = gpu_tune_eval(P, st))) return rc;
+  FMM_HIP_TRY(hipStreamSynchronize(st));
   return FMMLM_OK;
 }
 

@@ -305,6 +305,7 @@ int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
 int gpu_build_real_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_build_xlate_ops(fmmlm_plan_s* P, hipStream_t st);
 int gpu_tune_m2l(fmmlm_plan_s* P, hipStream_t st);
+int gpu_tune_eval(fmmlm_plan_s* P, hipStream_t st);
 constexpr int kM2LVariants = 6;  // FP32 M2L tile shapes the autotuner tries
 constexpr int kBatchShapes = 5;  // batched FP32 M2L tile shapes (each also persistent)
 int gpu_tune_batch(fmmlm_plan_s* P, hipStream_t st);
