@@ -21,11 +21,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "FMM matvecs/sec at N=1M 3-layer p=10 vs plain FP64 GPU FMM at <=1e-5 rel error"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_mfma32_3layer_N1048576_p10_traffic.md")
+# PMC summaries of HBM traffic per stage's kernel (see measured_traffic)
+TRAFFIC_FILES = {
+    "m2l": os.path.join(ROOT, "profiles", "m2l_mfma32_3layer_N1048576_p10_traffic.md"),
+    "p2p_free": os.path.join(ROOT, "profiles", "p2p_leaf_3layer_N1048576_p10_traffic.md"),
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_10863_amd", "csrc", "fmm.hip")
+# kernel that carries each stage of the FP32 form (one launch per evaluation)
+STAGE_KERNEL = {"m2l": "m2l_mfma32_kernel", "p2p_free": "p2p_leaf_kernel<float>"}
 CALIB_BYTES = 256 << 20  # plain device-to-device copy that scales the PMC byte counters
 PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32, vector and dense matrix (published), FLOP/s
+# Plain VALU issue rate with packed FP32 off (as this build compiles): 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 10 VALU
+# instructions per pair (3 sub, mul and 2 fma for r^2, rsq, compare, select, fma into the
+# sum) for the 11 flops counted per pair, so its ALU ceiling is 11/10 of the lane rate.
+VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
+P2P_INSTR_PER_PAIR = 10
+P2P_FLOPS_PER_PAIR = 11
+ALU_PEAK = {"p2p_free": VALU_LANE_RATE / P2P_INSTR_PER_PAIR * P2P_FLOPS_PER_PAIR}
 
 
 def stage_flops(stats, p, stage, rhs=1):
@@ -43,7 +57,7 @@ def _stage_flops1(stats, p, stage):
     if stage == "m2l_top":
         return 2.0 * full * full * stats["m2l_top_pairs"]
     if stage == "p2p_free":
-        return 11.0 * stats["p2p_free_pairs"]
+        return float(P2P_FLOPS_PER_PAIR) * stats["p2p_free_pairs"]
     if stage == "p2p_reaction":
         return 2.0 * stats["p2p_reaction_pairs"]
     if stage in ("p2m", "l2p"):
@@ -54,12 +68,12 @@ def _stage_flops1(stats, p, stage):
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, or None when the
-    summary is missing, is for another kernel, or the kernel source changed since."""
+    """HBM bytes per launch of the kernel of stage `kernel` from the committed PMC summary, or
+    None when the summary is missing, is for another stage, or the kernel source changed since."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
-    except OSError:
+        text = open(TRAFFIC_FILES[kernel]).read()
+    except (KeyError, OSError):
         return None
     fields = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith("traffic_"))
     fields = {k.strip(): v.strip() for k, v in fields.items()}
@@ -158,12 +172,16 @@ def main():
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
     flops = stage_flops(st, p, dom, args.rhs)
     achieved = flops / (avg[dom] * 1e-3) / 1e12
-    # the main M2L stage is one launch of the matrix-core GEMM kernel (FP32 MFMA)
-    kernel = "m2l_mfma32_kernel" if dom == "m2l" else dom
+    # the main M2L stage is one launch of the matrix-core GEMM kernel (FP32 MFMA); the free
+    # P2P stage one launch of the leaf-blocked VALU kernel
+    kernel = STAGE_KERNEL.get(dom, dom)
+    peak = (PEAK_FP32 if dom == "m2l" else ALU_PEAK.get(dom, PEAK_FP32)) / 1e12
     roofline = {"bound": "mfma" if dom == "m2l" else "alu", "kernel": kernel, "stage": dom,
-                "achieved": achieved, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / (PEAK_FP32 / 1e12), "traffic": measured_traffic(dom),
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(dom),
                 "flops_per_launch": flops, "avg_ms": avg[dom]}
+    if dom != "m2l":
+        roofline["peak_published_fp32"] = PEAK_FP32 / 1e12
 
     # CPU baseline: the oracle timed on a bounded slice of the error subsample (about 10-30 s
     # on the host's cores); the rest of the subsample completes the error reference
