@@ -33,11 +33,12 @@ CALIB_BYTES = 256 << 20  # plain device-to-device copy that scales the PMC byte 
 PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32, vector and dense matrix (published), FLOP/s
 # Plain VALU issue rate with packed FP32 off (as this build compiles): 256 CUs x 4 SIMDs x 16
-# lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 10 VALU
-# instructions per pair (3 sub, mul and 2 fma for r^2, rsq, compare, select, fma into the
-# sum) for the 11 flops counted per pair, so its ALU ceiling is 11/10 of the lane rate.
+# lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 8 VALU
+# instructions per pair (3 sub, mul and 2 fma for r^2, rsq, fma into the sum; the
+# zero-distance compare and select run only over a leaf's own points) for the 11 flops
+# counted per pair, so its ALU ceiling is 11/8 of the lane rate.
 VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
-P2P_INSTR_PER_PAIR = 10
+P2P_INSTR_PER_PAIR = 8
 P2P_FLOPS_PER_PAIR = 11
 ALU_PEAK = {"p2p_free": VALU_LANE_RATE / P2P_INSTR_PER_PAIR * P2P_FLOPS_PER_PAIR}
 
