@@ -199,6 +199,11 @@ typedef struct {
   double m2l_eval_ms[6];       /* FP32 form: time of a whole unprofiled evaluation (near field and
                                   sparse top levels on their streams beside the main M2L) with
                                   each tile shape; m2l_variant is the fastest of these */
+  double p2p_split_ms[5];      /* FP32 form: the same time with 100, 75, 50, 25 and 0 percent of
+                                  the free P2P leaves launched at the fork and the rest after the
+                                  main M2L launch ... */
+  int32_t p2p_split_pct;       /*   ... and the percentage kept (the fastest) */
+  int32_t reserved_stats3;
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);

@@ -292,12 +292,12 @@ void drop_graph(fmmlm_plan_s* P) {
 }
 
 void free_plan(fmmlm_plan_s* P) {
+  if (!P) return;
   drop_graph(P);
-  for (hipEvent_t e : {P->ev_q, P->ev_m, P->ev_near, P->ev_top})
+  for (hipEvent_t e : {P->ev_q, P->ev_m, P->ev_near, P->ev_top, P->ev_l})
     if (e) (void)hipEventDestroy(e);
   for (hipStream_t q : {P->s_near, P->s_top})
     if (q) (void)hipStreamDestroy(q);
-  if (!P) return;
   for (auto e : P->prof_ev) (void)hipEventDestroy(e);
   for (auto& b : P->bufs) hipFree(b.ptr);
   delete P;
@@ -975,6 +975,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   for (int64_t li = 0; li < P->nleaves; ++li)
     if (pptr[li + 1] > pptr[li]) plv.push_back((int32_t)li);
   P->n_pl_leaves = (int64_t)plv.size();
+  P->pl_split = P->n_pl_leaves;  // all at the fork until the evaluation-level tuner decides
   P->stats.p2p_free_pairs = B.free_pairs;
   P->stats.p2p_reaction_pairs = B.reac_pairs;
   // ---- leaf of every tree point, free-space point ranges
@@ -1130,7 +1131,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if ((rc = dev_alloc(P, &P->phin, P->NP))) return rc;
   FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_near, hipStreamNonBlocking));
   FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_top, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&P->ev_q, &P->ev_m, &P->ev_near, &P->ev_top})
+  for (hipEvent_t* e : {&P->ev_q, &P->ev_m, &P->ev_near, &P->ev_top, &P->ev_l})
     FMM_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;

@@ -214,6 +214,8 @@ struct fmmlm_plan_s {
   double* phin = nullptr;          // near-field potentials, tree order [NP]
   hipStream_t s_near = nullptr, s_top = nullptr;
   hipEvent_t ev_q = nullptr, ev_m = nullptr, ev_near = nullptr, ev_top = nullptr;
+  hipEvent_t ev_l = nullptr;       // main M2L launched (the rest of the near field may start)
+  int64_t pl_split = 0;            // free P2P leaves launched at the fork; the rest after the main M2L
   // graph mode: the captured evaluation and its arguments
   hipGraphExec_t gexec = nullptr;
   fmmlm::GraphKey gkey;

@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("m2l_variant", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64),
                 ("m2l_variant_ms", ctypes.c_double * 6), ("batch_variant", ctypes.c_int32),
                 ("reserved_stats2", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10),
-                ("m2l_eval_ms", ctypes.c_double * 6)]
+                ("m2l_eval_ms", ctypes.c_double * 6), ("p2p_split_ms", ctypes.c_double * 5),
+                ("p2p_split_pct", ctypes.c_int32), ("reserved_stats3", ctypes.c_int32)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
@@ -233,6 +234,7 @@ class Plan:
         out["m2l_variant_ms"] = list(out["m2l_variant_ms"])
         out["batch_variant_ms"] = list(out["batch_variant_ms"])
         out["m2l_eval_ms"] = list(out["m2l_eval_ms"])
+        out["p2p_split_ms"] = list(out["p2p_split_ms"])
         return out
 
     def tree(self, t):
