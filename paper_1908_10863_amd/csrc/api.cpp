@@ -940,7 +940,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   std::vector<int32_t> rp_t, rp_s, rp_c;
   // reaction rows: entry e's target rows have partial sums at rrow[e] + i;
   // work units of kRPUnitRows rows (entry, first row, target count)
-  std::vector<int32_t> rrow, runits;
+  std::vector<int32_t> rrow, runits, runits16;
   int64_t voff = 0, nrows = 0;
   for (int64_t li = 0; li < P->nleaves; ++li) {
     const int b = leaves[li];
@@ -955,6 +955,11 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
         runits.push_back((int32_t)rvoff.size());
         runits.push_back(r0);
         runits.push_back(tcnt);
+      }
+      for (int32_t r0 = 0; r0 < tcnt; r0 += 16) {  // batched FP32 form: 16-row matrix-core tiles
+        runits16.push_back((int32_t)rvoff.size());
+        runits16.push_back(r0);
+        runits16.push_back(tcnt);
       }
       rrow.push_back((int32_t)nrows);
       nrows += tcnt;
@@ -1024,6 +1029,11 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(rp_row, rrow); UP(rp_units, runits);
   P->n_rp_units = (int64_t)(runits.size() / 3);
   if ((rc = dev_alloc(P, &P->Prp, (size_t)std::max<int64_t>(nrows, 1)))) return rc;
+  if (P->fp32 && P->opts.max_rhs > 1) {
+    UP(rp_units16, runits16);
+    P->n_rp_units16 = (int64_t)(runits16.size() / 3);
+    if ((rc = dev_alloc(P, &P->Prb, (size_t)std::max<int64_t>(nrows, 1) * 64))) return rc;
+  }
   // recurrence coefficients of the regular solid harmonics (P2M, L2P):
   // [cidx(n,m)] a = sqrt((4n^2-1)/(n^2-m^2)), [nc + cidx] b = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)),
   // [2 nc + m] sqrt((2m+1)/(2m)) (m >= 1), [2 nc + p + 1 + m] sqrt(2m+3)

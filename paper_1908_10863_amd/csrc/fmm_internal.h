@@ -201,6 +201,9 @@ struct fmmlm_plan_s {
   int32_t *rp_units = nullptr;     // [3 * n_rp_units] (entry, first row, target count)
   int64_t n_rp_units = 0;
   double *Prp = nullptr;           // per (entry, target row) partial sums
+  int32_t *rp_units16 = nullptr;   // batched FP32 form: [3 * n_rp_units16] units of 16 rows
+  int64_t n_rp_units16 = 0;
+  float *Prb = nullptr;            // ... and their partial sums [entry row][64 vectors]
   // constants
   double *coefA = nullptr;         // A_n^m for n <= 2p, m <= n : [cidx]
   double *coefR = nullptr;         // solid-harmonic recurrence coefficients for n <= p (P2M, L2P)
