@@ -72,3 +72,35 @@ def test_fp32_full_size_sampled(dev, F, oracle_mod):
         e = relerr(phi[t], ref)
         _say(f"  mac={mac} rel L2 {e:.3e}")
         assert e <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_streams_and_tuning_do_not_change_results(dev, F, precision):
+    """An unprofiled evaluation runs the near field and the sparse top levels on
+    their own streams, with part of the free P2P after the main M2L and extra LDS
+    reserved by the P2P launch; a profiled one runs every stage in order on one
+    stream.  Each kernel's arithmetic is the same, so the results are bit-equal,
+    and so are those of every M2L tile shape (set_variants)."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say(f"overlapped == profiled, precision={precision}")
+    w = W.config(2, n=60000, seed=21)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=96,
+                  precision=precision, mac_d2=4)
+    st = plan.stats()
+    if precision == 1:
+        assert st["p2p_split_pct"] in (0, 25, 50, 75, 100)
+        assert all(t > 0 for t in st["p2p_split_ms"])
+        assert st["m2l_variant"] == int(np.argmin(st["m2l_eval_ms"]))
+    q = torch.tensor(w["q"][0], dtype=torch.float64, device=dev)
+    a = plan.eval(q).cpu().numpy()
+    plan.profile_begin(1)
+    b = plan.eval(q).cpu().numpy()
+    stages, n = plan.profile_end()
+    assert n == 1
+    assert np.array_equal(a, b)
+    if precision == 1:
+        for v in range(6):
+            plan.set_variants(m2l=v)
+            assert np.array_equal(plan.eval(q).cpu().numpy(), a), v
+    plan.close()
