@@ -1158,6 +1158,25 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       }
     P->nbbox = (int64_t)bb.size();
     if ((rc = dev_upload(P, &P->bbox, bb, st))) return rc;
+    if (P->fp32 && P->bbox_split > 0) {
+      // the FP64 top levels of the batched FP32 form: work items of at most
+      // kBatchTopItem entries of one box (few boxes, long entry lists)
+      std::vector<int32_t> items, iptr(1, 0);
+      for (int64_t bi = 0; bi < P->bbox_split; ++bi) {
+        const int32_t b = bb[bi];
+        for (int32_t e = mptr[b]; e < mptr[b + 1]; e += kBatchTopItem) {
+          items.push_back((int32_t)bi);
+          items.push_back(e);
+          items.push_back(std::min<int32_t>(e + kBatchTopItem, mptr[b + 1]));
+        }
+        iptr.push_back((int32_t)(items.size() / 3));
+      }
+      P->n_btop_items = (int64_t)(items.size() / 3);
+      if ((rc = dev_upload(P, &P->btop_items, items, st)) || (rc = dev_upload(P, &P->btop_iptr, iptr, st)))
+        return rc;
+      if ((rc = dev_alloc(P, &P->Pbtop, (size_t)std::max<int64_t>(P->n_btop_items, 1) * 64 * nrr)))
+        return rc;
+    }
     {
       auto octant = [&](int64_t b) {
         const HBox& bx = B.boxes[b];

@@ -18,6 +18,8 @@ constexpr int kMaxLevel = 20;  // 21-bit quantisation per axis
 // sparse top-level M2L: threads of a block, rounds of entries per work item
 constexpr int kSpThreads = 512;
 constexpr int kSpItemRounds = 4;
+// batched FP32 form, FP64 top levels: entries per work item
+constexpr int kBatchTopItem = 24;
 // reaction P2P: target rows per work unit (one wave, 8 lanes a row)
 constexpr int kRPUnitRows = 8;
 
@@ -201,6 +203,11 @@ struct fmmlm_plan_s {
   int32_t *rp_units = nullptr;     // [3 * n_rp_units] (entry, first row, target count)
   int64_t n_rp_units = 0;
   double *Prp = nullptr;           // per (entry, target row) partial sums
+  // batched FP32 form, FP64 top levels: work items (box-list index, first and
+  // end entry), per box a run of items, partials [item][64][(p+1)^2]
+  int32_t *btop_items = nullptr, *btop_iptr = nullptr;
+  int64_t n_btop_items = 0;
+  double* Pbtop = nullptr;
   int32_t *rp_units16 = nullptr;   // batched FP32 form: [3 * n_rp_units16] units of 16 rows
   int64_t n_rp_units16 = 0;
   float *Prb = nullptr;            // ... and their partial sums [entry row][64 vectors]
