@@ -1149,6 +1149,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (P->fp32 && (rc = gpu_tune_m2l(P, st))) return rc;
   if (G > 1) {
     if ((rc = dev_alloc(P, &P->qb64, P->NP * 64))) return rc;
+    if ((rc = dev_alloc(P, &P->qu, (size_t)P->N * 64))) return rc;
     if (P->fp32 && (rc = dev_alloc(P, &P->qb32, P->NP * 64))) return rc;
     std::vector<int32_t> bb;
     for (int64_t b = 0; b < P->NB; ++b)

@@ -182,7 +182,9 @@ struct fmmlm_plan_s {
   int32_t *bu_ptr = nullptr, *bu_src = nullptr, *bu_op = nullptr, *bu_boxes = nullptr;
   int32_t *bd_ptr = nullptr, *bd_src = nullptr, *bd_op = nullptr, *bd_boxes = nullptr;
   std::vector<int64_t> bu_lev, bd_lev;  // level l's targets: [lev[l], lev[l + 1])
-  double* qb64 = nullptr;          // [NP][64] vector-minor charges (FP64)
+  double* qb64 = nullptr;          // [NP][64] vector-minor charges (FP64); after the near field,
+                                   // the point-major potentials of the combine
+  double* qu = nullptr;            // [N][64] point-major charges in user order (batched gather)
   float* qb32 = nullptr;           // [NP][64] (FP32 form)
   int64_t ntiles = 0, nsteps = 0;
   int32_t *tile_ptr = nullptr, *tile_tgt = nullptr, *tile_level = nullptr;
