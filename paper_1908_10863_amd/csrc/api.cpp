@@ -1094,7 +1094,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (P->fp32) {
     const size_t nr = (size_t)(P->p + 1) * (P->p + 1);
     if ((rc = dev_alloc(P, &P->Tfree32, (size_t)std::max<int64_t>(P->nops, 1) * P->nrk * 32 * P->mrt))) return rc;
-    if (std::min(P->opts.max_rhs, 64) == 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nr))) return rc;
+    // single-vector FP32 sources: rows padded to nrk (aligned, zero past nr)
+    if (std::min(P->opts.max_rhs, 64) == 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * P->nrk))) return rc;
+    (void)nr;
     if ((rc = dev_alloc(P, &P->qt32, P->NP))) return rc;
     if ((rc = dev_alloc(P, &P->pxh, P->NP)) || (rc = dev_alloc(P, &P->pxl, P->NP)) ||
         (rc = dev_alloc(P, &P->pyh, P->NP)) || (rc = dev_alloc(P, &P->pyl, P->NP)) ||
@@ -1145,7 +1147,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     FMM_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
-  if (P->fp32 && G > 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * nrr * G))) return rc;
+  if (P->fp32 && G > 1 &&
+      (rc = dev_alloc(P, &P->M32, std::max((size_t)P->NB * nrr * G, (size_t)P->NB * P->nrk))))
+    return rc;
   if (P->fp32 && (rc = gpu_tune_m2l(P, st))) return rc;
   if (G > 1) {
     if ((rc = dev_alloc(P, &P->qb64, P->NP * 64))) return rc;
