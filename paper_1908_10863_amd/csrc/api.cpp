@@ -1147,9 +1147,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     FMM_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
-  if (P->fp32 && G > 1 &&
-      (rc = dev_alloc(P, &P->M32, std::max((size_t)P->NB * nrr * G, (size_t)P->NB * P->nrk))))
-    return rc;
+  // FP32 sources of the batched form: [vector][box][nrk] (aligned rows, zero past nr)
+  if (P->fp32 && G > 1 && (rc = dev_alloc(P, &P->M32, (size_t)P->NB * P->nrk * G))) return rc;
   if (P->fp32 && (rc = gpu_tune_m2l(P, st))) return rc;
   if (G > 1) {
     if ((rc = dev_alloc(P, &P->qb64, P->NP * 64))) return rc;
