@@ -849,7 +849,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   // ---- M2M / L2L as GEMMs over tiles of up to xl_tile_cols target boxes of one
   // level: M2M tiles hold parents (one step per child octant present, source
   // = that child, operator = octant); L2L tiles hold children of one octant
-  // (one step, source = the parent, operator 8 + octant).  One unit per step.
+  // (one step, source = the parent, operator 8 + octant).  One unit per step,
+  // so an L2L tile is one unit, added with it (the GEMM adds L2L products into
+  // the children directly).
   {
     // narrow tiles: a level's translations are few, so more and smaller blocks
     const int TBc = P->xl_tile_cols;
