@@ -224,6 +224,13 @@ def main():
         "stage_ms": avg, "plan_seconds": st["plan_seconds"],
         "counts": {k: st[k] for k in ("n_boxes", "n_leaves", "m2l_free_pairs", "m2l_reaction_pairs",
                                       "p2p_free_pairs", "p2p_reaction_pairs", "max_level")},
+        # the plan's autotuner: main M2L shape (launch alone, then whole evaluations)
+        # and the near-field split, each in ms
+        "tuning": {"m2l_variant": st["m2l_variant"],
+                   "m2l_variant_ms": [round(x, 4) for x in st["m2l_variant_ms"]],
+                   "m2l_eval_ms": [round(x, 4) for x in st["m2l_eval_ms"]],
+                   "p2p_split_pct": st["p2p_split_pct"],
+                   "p2p_split_ms": [round(x, 4) for x in st["p2p_split_ms"]]},
     }
     print(json.dumps(rec))
 
