@@ -141,6 +141,62 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
  * device first so that in-flight evaluations finish. */
 int fmm_layered_destroy(fmmlm_plan_t plan);
 
+/* ---- iterative solve around the matvec ------------------------------------------ */
+/*
+ * The paper's motivating application (Sec. 1): a dense system whose product is
+ * the layered-media potential, solved by GMRES with the FMM as the matvec.
+ * fmm_layered_solve solves the second-kind system
+ *
+ *   (diag(diag) + G) x = b,      G x = fmm_layered_eval(x) (both parts),
+ *
+ * by restarted GMRES (Saad & Schultz, SIAM J. Sci. Stat. Comput. 7 (1986)):
+ * Arnoldi with classical Gram-Schmidt applied twice, Givens rotations for the
+ * least-squares problem, the true residual recomputed at each restart.  All
+ * vector work runs on the device in FP64 with fixed-order reductions (the
+ * result is reproducible for a given plan); the small Hessenberg problem is
+ * solved on the host, which reads k + 2 values per Arnoldi step.
+ *
+ *  diag       device, n values in user order, or NULL for a zero diagonal
+ *             (e.g. the self term of a collocation panel)
+ *  b          device, n values (user order)
+ *  x          device, n values: the initial guess on entry (ignored when
+ *             opts.zero_guess), the solution on return; must not overlap b
+ *  opts       NULL for the defaults (restart 30, max_iters 300, tol 1e-6,
+ *             zero_guess 0)
+ *  hip_stream all device work is enqueued here; the call returns after it has
+ *             finished (it synchronises hip_stream once per Arnoldi step)
+ *  info       host, filled on FMMLM_OK (also when not converged)
+ *
+ * The reachable tolerance is bounded by the plan's matvec accuracy (about
+ * 1e-5 relative for the FP32 form at p = 10) times the system's conditioning.
+ * Workspace: (restart + 1) n doubles plus small buffers, allocated and freed
+ * by the call.  Evaluations of the plan must not overlap the call.
+ * Errors: FMMLM_EINVAL (null plan, b, x or info; restart outside 1..256;
+ * max_iters < 1; tol not in (0, 1); x overlapping b), FMMLM_ENOMEM,
+ * FMMLM_EDEVICE.  With the plan's graph option every step captures anew (the
+ * vectors change from step to step): leave it off for solves.
+ */
+typedef struct {
+  int32_t restart;     /* Krylov vectors per cycle, 1..256 (default 30) */
+  int32_t max_iters;   /* Arnoldi steps in all, >= 1 (default 300) */
+  double tol;          /* stop when ||b - (diag + G) x|| <= tol ||b|| (default 1e-6) */
+  int32_t zero_guess;  /* 1: start from x = 0 (no matvec for the first residual) */
+  int32_t reserved;
+} fmmlm_solve_opts;
+
+typedef struct {
+  int32_t iters;       /* Arnoldi steps (one matvec each) */
+  int32_t matvecs;     /* evaluations in all (Arnoldi steps + true residuals) */
+  int32_t cycles;      /* restart cycles run */
+  int32_t converged;   /* 1 when the final true residual meets tol */
+  double relres;       /* final true ||b - (diag + G) x|| / ||b|| */
+  double relres_est;   /* the GMRES estimate at the last Arnoldi step */
+  double seconds;      /* wall time of the call */
+} fmmlm_solve_info;
+
+int fmm_layered_solve(fmmlm_plan_t plan, const double* diag, const double* b, double* x,
+                      const fmmlm_solve_opts* opts, void* hip_stream, fmmlm_solve_info* info);
+
 /* Static text for an error code, followed by the calling thread's last HIP
  * error message when there is one.  Never NULL. */
 const char* fmm_layered_strerror(int code);

@@ -18,6 +18,9 @@ Contents and the passage each follows:
                         composite Gauss-Legendre quadrature.
 * ``reaction_image3``  the same kernel for three layers as an image series.
 * ``potential``        direct O(N * targets) sum of eq. totalinteraction.
+* ``matrix``           the same pair values as a dense N x N matrix.
+* ``solve_dense``      the solution of (diag + G) x = b by a dense LU solve: what
+                        an iterative solve around the FMM matvec computes (Sec. 1).
 * ``sommerfeld_sigma1`` closed form of S^n I_nm for sigma == 1 (Sec. 3.4, the
                         identity used for Table 3.1).
 * ``sommerfeld_image3`` S^n I_nm for a three-layer density: image series of the
@@ -84,6 +87,9 @@ def _load():
         lib.oracle_potential.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, dp, dp, dp, ip,
                                          dp, ctypes.c_int64, lp, ctypes.c_int, ctypes.c_int, dp]
         lib.oracle_potential.restype = ctypes.c_int
+        lib.oracle_matrix.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, dp, dp, dp, ip,
+                                      ctypes.c_int64, lp, ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.oracle_matrix.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -187,6 +193,39 @@ def potential(d, eps, x, y, z, layer, q, targets=None, method="auto", parts=3) -
     if rc:
         raise ValueError(f"oracle_potential failed ({rc})")
     return out
+
+
+def matrix(d, eps, x, y, z, layer, method="auto", parts=3) -> np.ndarray:
+    """The dense N x N matrix of eq. totalinteraction: G[i, j] is the potential at
+    point i of a unit charge at point j (free part for j != i in the same layer,
+    reaction part for every j), so that G @ q == potential(q)."""
+    d = _f64(d)
+    eps = _f64(eps)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    layer = np.ascontiguousarray(np.asarray(layer, dtype=np.int32))
+    n = len(x)
+    targets = np.arange(n, dtype=np.int64)
+    if method == "auto":
+        method = "image3" if len(d) == 2 else "quad"
+    m = {"quad": 0, "image3": 1}[method]
+    G = np.zeros((n, n))
+    scratch = np.zeros(n)
+    rc = _load().oracle_matrix(len(d), _dp(d), _dp(eps), n, _dp(x), _dp(y), _dp(z),
+                               layer.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n,
+                               targets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), m, int(parts),
+                               _dp(scratch), _dp(G))
+    if rc:
+        raise ValueError(f"oracle_matrix failed ({rc})")
+    return G
+
+
+def solve_dense(G, diag, b) -> np.ndarray:
+    """The solution x of the second-kind system (diag(diag) + G) x = b, the
+    product whose G part the FMM evaluates (the iterative solve of the
+    paper's motivating application, Sec. 1), by a dense LU solve."""
+    A = np.array(G, dtype=np.float64, copy=True)
+    A[np.diag_indices_from(A)] += _f64(diag)
+    return np.linalg.solve(A, _f64(b))
 
 
 # --------------------------------------------------------------------------

@@ -356,11 +356,15 @@ static double zeta_of(const double* d, int lt, int ls, int a, int b, double z,
 /*   parts   : bit 0 free space, bit 1 reaction                              */
 /* Targets are indices into the N points; phi_out has nt entries.            */
 /* ------------------------------------------------------------------------ */
-int oracle_potential(int L, const double* d, const double* eps, int64_t n,
-                     const double* x, const double* y, const double* z,
-                     const int32_t* layer, const double* q, int64_t nt,
-                     const int64_t* targets, int method, int parts,
-                     double* phi_out) {
+/* Direct sum at the selected targets.  With mat_out non-null the pair values
+ * themselves are stored as well, mat_out[ti * n + j] = the potential at
+ * target ti of a unit charge at j (0 where no part applies); q may then be
+ * NULL (unit charges). */
+static int potential_impl(int L, const double* d, const double* eps, int64_t n,
+                          const double* x, const double* y, const double* z,
+                          const int32_t* layer, const double* q, int64_t nt,
+                          const int64_t* targets, int method, int parts,
+                          double* phi_out, double* mat_out) {
   if (L < 1 || L > OR_MAXL) return -1;
   if (method == 1 && L != 2) return -1;
   const int ncomp = (L + 1) * (L + 1) * 4;
@@ -433,12 +437,17 @@ int oracle_potential(int L, const double* d, const double* eps, int64_t n,
     const int li = layer[i];
     double fs = 0.0, fc = 0.0; /* free part, Neumaier */
     double rs = 0.0, rc = 0.0; /* reaction part, Neumaier */
+    double* mrow = mat_out ? mat_out + ti * n : NULL;
     for (int64_t j = 0; j < n; ++j) {
       const double dx = xi - x[j], dy = yi - y[j];
       const int lj = layer[j];
+      const double qj = q ? q[j] : 1.0;
+      if (mrow) mrow[j] = 0.0;
       if ((parts & 1) && lj == li && j != i) {
         const double dz = zi - z[j];
-        const double f = q[j] / (4.0 * OR_PI * sqrt(dx * dx + dy * dy + dz * dz));
+        const double g = 1.0 / (4.0 * OR_PI * sqrt(dx * dx + dy * dy + dz * dz));
+        if (mrow) mrow[j] += g;
+        const double f = qj / (4.0 * OR_PI * sqrt(dx * dx + dy * dy + dz * dz));
         const double t = fs + f;
         if (fabs(fs) >= fabs(f)) fc += (fs - t) + f; else fc += (f - t) + fs;
         fs = t;
@@ -474,7 +483,8 @@ int oracle_potential(int L, const double* d, const double* eps, int64_t n,
               v += acc / (4.0 * OR_PI);
             }
         }
-        const double f = q[j] * v;
+        if (mrow) mrow[j] += v;
+        const double f = qj * v;
         const double t = rs + f;
         if (fabs(rs) >= fabs(f)) rc += (rs - t) + f; else rc += (f - t) + rs;
         rs = t;
@@ -489,4 +499,22 @@ int oracle_potential(int L, const double* d, const double* eps, int64_t n,
   free(ishift);
   free(icnt);
   return err;
+}
+
+int oracle_potential(int L, const double* d, const double* eps, int64_t n,
+                     const double* x, const double* y, const double* z,
+                     const int32_t* layer, const double* q, int64_t nt,
+                     const int64_t* targets, int method, int parts,
+                     double* phi_out) {
+  return potential_impl(L, d, eps, n, x, y, z, layer, q, nt, targets, method, parts, phi_out, NULL);
+}
+
+/* The dense matrix of eq. totalinteraction: G[ti * n + j] is the potential at
+ * target ti of a unit charge at j (free part for j != i in the same layer, the
+ * reaction part for every j).  phi_scratch: nt doubles. */
+int oracle_matrix(int L, const double* d, const double* eps, int64_t n,
+                  const double* x, const double* y, const double* z,
+                  const int32_t* layer, int64_t nt, const int64_t* targets,
+                  int method, int parts, double* phi_scratch, double* G) {
+  return potential_impl(L, d, eps, n, x, y, z, layer, NULL, nt, targets, method, parts, phi_scratch, G);
 }

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmmlm.so")
-SOURCES = ["api.cpp", "tree.hip", "sommerfeld.hip", "fmm.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "tree.hip", "sommerfeld.hip", "fmm.hip", "mlp.hip", "solve.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every kernel

@@ -46,6 +46,17 @@ class TrainReport(ctypes.Structure):
                 ("yscale", ctypes.c_double), ("ladder_fit", ctypes.c_double)]
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("zero_guess", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("relres_est", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_tree_points", ctypes.c_int64),
                 ("n_trees", ctypes.c_int32), ("p", ctypes.c_int32), ("max_level", ctypes.c_int32),
@@ -76,7 +87,7 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_create_for_plan", "fmm_layered_surrogate_train",
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
-           "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants"]
+           "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -104,6 +115,8 @@ def lib():
     L.fmm_layered_eval.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                    ctypes.c_uint32, vp]
     L.fmm_layered_eval.restype = ctypes.c_int
+    L.fmm_layered_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
+    L.fmm_layered_solve.restype = ctypes.c_int
     L.fmm_layered_destroy.argtypes = [vp]
     L.fmm_layered_destroy.restype = ctypes.c_int
     L.fmm_layered_strerror.argtypes = [ctypes.c_int]
@@ -222,6 +235,24 @@ class Plan:
                                     _stream_handle(stream))
         check(rc)
         return out.reshape(q.shape)
+
+    def solve(self, b, diag=None, x0=None, tol=1e-6, restart=30, max_iters=300, stream=None):
+        """GMRES for (diag(diag) + G) x = b with G this plan's matvec
+        (fmm_layered_solve).  b, diag, x0: CUDA float64 tensors [n] (user order);
+        x0 None starts from zero.  Returns (x, info dict)."""
+        import torch
+        for name, t in (("b", b), ("diag", diag), ("x0", x0)):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.numel() == self.n):
+                raise ValueError(f"{name} must be a CUDA float64 tensor of length n")
+        b = b.contiguous()
+        x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
+        d = None if diag is None else diag.contiguous()
+        o = SolveOpts(int(restart), int(max_iters), float(tol), 1 if x0 is None else 0, 0)
+        info = SolveInfo()
+        check(lib().fmm_layered_solve(self._h, None if d is None else ctypes.c_void_p(d.data_ptr()),
+                                      ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.byref(o), _stream_handle(stream), ctypes.byref(info)))
+        return x, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
     def set_variants(self, m2l=-1, batch=-1):
         """Override the autotuner's kernel variants (see fmm_layered_plan_set_variants)."""

@@ -117,3 +117,74 @@ def config(idx: int, n: int | None = None, seed: int | None = None):
     else:
         raise ValueError(idx)
     return w
+
+
+# ---- capacitance-style systems ---------------------------------------------------
+# Conductors (axis-aligned bars) in the three-layer medium: two parallel wires in
+# the middle layer, a crossing wire above the top interface and a plate below
+# the bottom one, each shifted by a seeded offset of at most 0.02 (every face
+# stays at least 0.13 from an interface).  (x0, x1, y0, y1, z0, z1, layer)
+_CONDUCTORS = (
+    (-0.5, 0.5, -0.20, -0.10, -0.55, -0.45, 1),
+    (-0.5, 0.5, 0.10, 0.20, -0.55, -0.45, 1),
+    (-0.05, 0.05, -0.5, 0.5, 0.15, 0.25, 0),
+    (-0.6, 0.6, -0.6, 0.6, -1.35, -1.25, 2),
+)
+
+
+def _rect_self_integral(a, b):
+    """int over [-a, a] x [-b, b] of dA / sqrt(x^2 + y^2) (closed form)."""
+    r = np.hypot(a, b)
+    return 4.0 * (a * np.log((b + r) / a) + b * np.log((a + r) / b))
+
+
+def capacitance(n: int = 1500, seed: int = 7):
+    """Points at the centres of about n rectangular panels covering the conductors'
+    surfaces (spacing h = sqrt(total area / n) on every face), with
+
+      diag[i]  the self term of panel i: the potential at its centre of a unit
+               charge spread uniformly over it, 1/(4 pi A) int dA / r
+      b[i]     1 on conductor 0, 0 elsewhere (the first column of the
+               capacitance matrix: conductor 0 at unit potential)
+      cond[i]  the conductor of panel i, area[i] its area.
+
+    The system (diag + G) x = b is the collocation form of the first-kind
+    integral equation for the surface charge, in the library's normalisation
+    (free part 1/(4 pi r))."""
+    rng = np.random.default_rng(seed)
+    boxes = []
+    for (x0, x1, y0, y1, z0, z1, lay) in _CONDUCTORS:
+        s = rng.uniform(-0.02, 0.02, 3)
+        boxes.append((x0 + s[0], x1 + s[0], y0 + s[1], y1 + s[1], z0 + s[2], z1 + s[2], lay))
+    total = 0.0
+    for (x0, x1, y0, y1, z0, z1, _) in boxes:
+        ex, ey, ez = x1 - x0, y1 - y0, z1 - z0
+        total += 2.0 * (ex * ey + ex * ez + ey * ez)
+    h = float(np.sqrt(total / n))
+    X, Y, Z, LAY, COND, AREA, DIAG = [], [], [], [], [], [], []
+    for c, (x0, x1, y0, y1, z0, z1, lay) in enumerate(boxes):
+        lo, hi = (x0, y0, z0), (x1, y1, z1)
+        for axis in range(3):          # the face's normal axis
+            u, v = [a for a in range(3) if a != axis]
+            nu = max(1, int(round((hi[u] - lo[u]) / h)))
+            nv = max(1, int(round((hi[v] - lo[v]) / h)))
+            du, dv = (hi[u] - lo[u]) / nu, (hi[v] - lo[v]) / nv
+            cu = lo[u] + (np.arange(nu) + 0.5) * du
+            cv = lo[v] + (np.arange(nv) + 0.5) * dv
+            gu, gv = np.meshgrid(cu, cv, indexing="ij")
+            self_term = _rect_self_integral(du / 2, dv / 2) / (4.0 * np.pi * du * dv)
+            for side in (lo[axis], hi[axis]):
+                P = np.zeros((3, gu.size))
+                P[axis] = side
+                P[u] = gu.ravel()
+                P[v] = gv.ravel()
+                X.append(P[0]); Y.append(P[1]); Z.append(P[2])
+                LAY.append(np.full(gu.size, lay, np.int32))
+                COND.append(np.full(gu.size, c, np.int32))
+                AREA.append(np.full(gu.size, du * dv))
+                DIAG.append(np.full(gu.size, self_term))
+    cond = np.concatenate(COND)
+    return dict(d=list(THREE_LAYER_D), eps=list(THREE_LAYER_EPS), x=np.concatenate(X), y=np.concatenate(Y),
+                z=np.concatenate(Z), layer=np.concatenate(LAY), cond=cond, area=np.concatenate(AREA),
+                diag=np.concatenate(DIAG), b=(cond == 0).astype(np.float64), h=h,
+                name=f"capacitance: 4 conductors in the 3-layer medium, {len(cond)} panels")

@@ -115,6 +115,12 @@ def test_eval_rejects_null_plan(L):
     assert L.fmm_layered_eval(None, 1, None, 1, None, 1, 3, None) == -1
 
 
+def test_solve_rejects_null_plan(L):
+    from paper_1908_10863_amd import fmmlm
+    info = fmmlm.SolveInfo()
+    assert L.fmm_layered_solve(None, None, None, None, None, None, ctypes.byref(info)) == -1
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_1908_10863_amd import fmmlm
     monkeypatch.setattr(fmmlm, "_lib", None)

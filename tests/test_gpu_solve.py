@@ -1,0 +1,153 @@
+"""GMRES around the FMM matvec (fmm_layered_solve) against the oracle's dense solve.
+
+Capacitance-style system (diag + G) x = b on 4 conductors in the 3-layer medium
+(1600 panels: six full blocks of 256 and a ragged 64).  The solution's error is
+bounded by the system's condition number (about 95) times the matvec's error:
+  FP64 form, p = 12, mac 6 (matvec error about 4e-8): rel L2 <= 1e-5;
+  FP32 form, p = 10, mac 4 (matvec error about 4e-6): rel L2 <= 2e-3.
+The oracle also measures the GPU solution's residual with the exact operator.
+Edge cases: b = 0, an initial guess that already meets the tolerance, too few
+iterations, GMRES(1), the largest restart, no diagonal, invalid options, and
+bit-for-bit reproducibility.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1908_10863_amd import fmmlm
+    fmmlm.lib()
+    return fmmlm
+
+
+@pytest.fixture(scope="module")
+def small(oracle_mod):
+    from paper_1908_10863_amd import workloads as W
+    w = W.capacitance(1500, seed=7)
+    G = oracle_mod.matrix(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], method="image3")
+    xref = oracle_mod.solve_dense(G, w["diag"], w["b"])
+    return w, G, xref
+
+
+def _plan(F, w, precision, p, mac, cap):
+    return F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p, leaf_cap=cap,
+                  precision=precision, mac_d2=mac)
+
+
+def _t(dev, a):
+    import torch
+    return torch.tensor(np.asarray(a, np.float64), device=dev)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def plan64(F, small):
+    w = small[0]
+    pl = _plan(F, w, 0, 12, 6, 32)
+    yield pl
+    pl.close()
+
+
+def test_fp64_solve_matches_dense_solve(dev, plan64, small):
+    import torch
+    w, G, xref = small
+    assert len(w["x"]) == 1600
+    b, d = _t(dev, w["b"]), _t(dev, w["diag"])
+    _say("FP64 solve, 1600 panels")
+    x, info = plan64.solve(b, diag=d, tol=1e-9, restart=30, max_iters=400)
+    xs = x.cpu().numpy()
+    e = relerr(xs, xref)
+    r = w["b"] - (G @ xs + w["diag"] * xs)
+    _say(f"  {info}  rel err {e:.2e}  exact-operator residual {np.linalg.norm(r) / np.linalg.norm(w['b']):.2e}")
+    assert info["converged"] == 1 and info["relres"] <= 1e-9
+    assert info["matvecs"] == info["iters"] + info["cycles"]
+    assert e <= 1e-5
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(w["b"])
+    # reproducible bit for bit
+    x2, info2 = plan64.solve(b, diag=d, tol=1e-9, restart=30, max_iters=400)
+    assert torch.equal(x, x2)
+    assert {k: v for k, v in info.items() if k != "seconds"} == {k: v for k, v in info2.items() if k != "seconds"}
+
+
+def test_fp32_solve_matches_dense_solve(dev, F, small):
+    w, G, xref = small
+    pl = _plan(F, w, 1, 10, 4, 32)
+    _say("FP32 solve, 1600 panels")
+    x, info = pl.solve(_t(dev, w["b"]), diag=_t(dev, w["diag"]), tol=1e-5, restart=30, max_iters=400)
+    pl.close()
+    xs = x.cpu().numpy()
+    e = relerr(xs, xref)
+    _say(f"  {info}  rel err {e:.2e}")
+    assert info["converged"] == 1 and info["relres"] <= 1e-5
+    assert e <= 2e-3
+
+
+def test_edge_cases(dev, plan64, small):
+    import torch
+    w, G, xref = small
+    n = len(w["x"])
+    b, d = _t(dev, w["b"]), _t(dev, w["diag"])
+    # b = 0: x = 0 without a matvec, even from a nonzero guess
+    x, info = plan64.solve(torch.zeros(n, dtype=torch.float64, device=dev), diag=d,
+                           x0=torch.ones(n, dtype=torch.float64, device=dev))
+    assert info["iters"] == 0 and info["matvecs"] == 0 and info["converged"] == 1
+    assert not x.any()
+    # a guess that already meets the tolerance: one residual, x unchanged
+    x0 = _t(dev, xref)
+    x, info = plan64.solve(b, diag=d, x0=x0, tol=1e-4)
+    assert info["iters"] == 0 and info["matvecs"] == 1 and info["converged"] == 1
+    assert torch.equal(x, x0)
+    # too few iterations: returns normally, not converged, residual reduced
+    x, info = plan64.solve(b, diag=d, tol=1e-9, max_iters=3)
+    assert info["iters"] == 3 and info["converged"] == 0 and 1e-9 < info["relres"] < 1.0
+    # GMRES(1): one step per cycle
+    x, info = plan64.solve(b, diag=d, tol=1e-9, restart=1, max_iters=12)
+    assert info["cycles"] == 12 and info["iters"] == 12 and info["matvecs"] == 24
+    assert info["relres"] < 1.0
+    # the largest restart: no restart before convergence
+    x, info = plan64.solve(b, diag=d, tol=1e-9, restart=256, max_iters=256)
+    assert info["converged"] == 1 and info["cycles"] == 1
+    assert relerr(x.cpu().numpy(), xref) <= 1e-5
+
+
+def test_no_diagonal_residual_is_exact_operator_residual(dev, plan64, small):
+    """diag = None solves the first-kind system G x = b; the reported residual is
+    the FMM's, which agrees with the exact operator's to the matvec's error."""
+    w, G, xref = small
+    x, info = plan64.solve(_t(dev, w["b"]), diag=None, tol=1e-9, max_iters=30)
+    xs = x.cpu().numpy()
+    r = np.linalg.norm(w["b"] - G @ xs) / np.linalg.norm(w["b"])
+    _say(f"  first kind: {info}  exact-operator residual {r:.3e}")
+    assert info["iters"] == 30 and info["relres"] < 1.0
+    assert abs(info["relres"] - r) <= 1e-3 * r + 1e-9
+
+
+def test_invalid_options(dev, plan64, small):
+    w = small[0]
+    b = _t(dev, w["b"])
+    for kw in (dict(restart=0), dict(restart=257), dict(tol=0.0), dict(tol=1.0), dict(max_iters=0)):
+        with pytest.raises(Exception):
+            plan64.solve(b, **kw)
+    with pytest.raises(ValueError):
+        plan64.solve(b[:10])
