@@ -6,7 +6,10 @@ resident in HBM before the timed region.  A step is one fmm_layered_eval (free
 space + all 16 reaction components).  The K timed steps run as in production
 (near field and sparse top levels on their own streams); a second pass of K
 profiled steps, whose stages run in order on one stream, gives the per-stage
-times and the dominant kernel's time.  Prints one JSON line.
+times and the dominant kernel's time.  The line also carries `solve`: restarted
+GMRES on a capacitance-style system (conductor panels in the same medium, about
+1M panels) with the FP32 form as the matvec, the method's application.  Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -132,6 +135,46 @@ def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1):
             "phi": phi if rhs == 1 else phi[0]}
 
 
+def run_solve(fmmlm, workloads, dev, n, restart, tol, reps):
+    """GMRES solves of the capacitance-style system (diag + G) x = b on conductor
+    panels in the three-layer medium, the FP32 form as the matvec (p = 10,
+    mac_d2 = 4, leaf cap 192); the best of `reps` timed solves after one warm-up."""
+    import torch
+    w = workloads.capacitance(n)
+    plan = fmmlm.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=192,
+                      precision=fmmlm.FMMLM_FP32_COMPENSATED, mac_d2=4)
+    b = torch.tensor(w["b"], device=dev)
+    d = torch.tensor(w["diag"], device=dev)
+    out = torch.empty_like(b)
+    for _ in range(3):
+        plan.eval(b, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        plan.eval(b, out=out)
+    torch.cuda.synchronize()
+    ms_eval = (time.perf_counter() - t0) / 20 * 1e3
+    x, info = plan.solve(b, diag=d, tol=tol, restart=restart, max_iters=1000)
+    best = None
+    for _ in range(reps):
+        x, info = plan.solve(b, diag=d, tol=tol, restart=restart, max_iters=1000)
+        if best is None or info["seconds"] < best["seconds"]:
+            best = info
+    plan.close()
+    on0 = torch.tensor(w["cond"] == 0, device=dev)
+    ms = best["seconds"] * 1e3
+    res = {"workload": w["name"], "n": len(w["x"]), "form": "fp32-compensated p=10 mac_d2=4 leaf cap 192",
+           "restart": restart, "tol": tol, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+           "iters": best["iters"], "matvecs": best["matvecs"], "cycles": best["cycles"],
+           "converged": bool(best["converged"]), "relres": best["relres"], "ms_per_eval": ms_eval,
+           "eval_share": best["matvecs"] * ms_eval / ms,
+           "ms_per_step_vector_work": (ms - best["matvecs"] * ms_eval) / max(best["iters"], 1),
+           # physical charge on conductor 0 at unit potential (eps of its layer times the charge)
+           "C00": float(x[on0].sum()) * w["eps"][int(w["layer"][w["cond"] == 0][0])]}
+    print(f"[bench] solve: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +190,8 @@ def main():
                     help="oracle targets of the error subsample")
     ap.add_argument("--cpu-timed", type=int, default=1536,
                     help="first targets of the subsample timed as the CPU baseline")
+    ap.add_argument("--solve-n", type=int, default=1048576,
+                    help="panels of the capacitance-style GMRES solve (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
@@ -168,6 +213,8 @@ def main():
                     args.warmup, dev)
     form = run_form(fmmlm, w, p, args.leaf_cap, args.mac, fmmlm.FMMLM_FP32_COMPENSATED, args.steps,
                     args.warmup, dev, rhs=args.rhs)
+    solve = (run_solve(fmmlm, workloads, dev, args.solve_n, restart=100, tol=1e-5, reps=3)
+             if args.solve_n > 0 else None)
     st = form["stats"]
     avg = form["stages"]
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
@@ -226,6 +273,7 @@ def main():
                                       "p2p_free_pairs", "p2p_reaction_pairs", "max_level")},
         # the plan's autotuner: main M2L shape (launch alone, then whole evaluations)
         # and the near-field split, each in ms
+        "solve": solve,
         "tuning": {"m2l_variant": st["m2l_variant"],
                    "m2l_variant_ms": [round(x, 4) for x in st["m2l_variant_ms"]],
                    "m2l_eval_ms": [round(x, 4) for x in st["m2l_eval_ms"]],
