@@ -10,6 +10,9 @@ Contents and the passage each follows:
 
 * ``sigma``            reaction densities sigma^{ab}_{l l'}(k) by a direct solve of
                         the interface system (App. A, interface conditions).
+* ``sigma_ab``, ``potential_ab``  the same for general interface conditions
+                        a u and b du/dz continuous (App. A's general
+                        conditions; classic a = 1, b = eps), direct solve.
 * ``sigma3``           the explicit three-layer densities (App. A,
                         eqs. densitythreelayer1-3, with the two readings listed
                         in the design notes).
@@ -90,6 +93,12 @@ def _load():
         lib.oracle_matrix.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, dp, dp, dp, ip,
                                       ctypes.c_int64, lp, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.oracle_matrix.restype = ctypes.c_int
+        lib.oracle_sigma_ab.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, dp]
+        lib.oracle_sigma_ab.restype = ctypes.c_int
+        lib.oracle_potential_ab.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int64, dp, dp, dp, ip,
+                                            dp, ctypes.c_int64, lp, ctypes.c_int, dp]
+        lib.oracle_potential_ab.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -119,6 +128,40 @@ def sigma(d, eps, lt: int, ls: int, k: float) -> np.ndarray:
     rc = _load().oracle_sigma(len(d), _dp(d), _dp(eps), lt, ls, float(k), _dp(out))
     if rc:
         raise ValueError(f"oracle_sigma failed ({rc})")
+    return out
+
+
+def sigma_ab(d, a, b, lt: int, ls: int, k: float) -> np.ndarray:
+    """sigma^{ab}_{lt,ls}(k) for the general interface conditions of App. A,
+    a_{i-1} u_{i-1} = a_i u_i and b_{i-1} u'_{i-1} = b_i u'_i at every interface
+    (classic: a = 1, b = eps), by the same direct solve; indexed like sigma."""
+    d = _f64(d)
+    a = _f64(a)
+    b = _f64(b)
+    out = np.zeros(4)
+    rc = _load().oracle_sigma_ab(len(d), _dp(d), _dp(a), _dp(b), int(lt), int(ls), float(k), _dp(out))
+    if rc:
+        raise ValueError(f"oracle_sigma_ab failed ({rc})")
+    return out
+
+
+def potential_ab(d, a, b, x, y, z, layer, q, targets=None, parts=3) -> np.ndarray:
+    """Direct sum of eq. totalinteraction for the general interface conditions
+    (coefficients a, b), reaction kernels by quadrature."""
+    d, a, b = _f64(d), _f64(a), _f64(b)
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    layer = np.ascontiguousarray(np.asarray(layer, dtype=np.int32))
+    n = len(x)
+    if targets is None:
+        targets = np.arange(n, dtype=np.int64)
+    targets = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    out = np.zeros(len(targets))
+    rc = _load().oracle_potential_ab(len(d), _dp(d), _dp(a), _dp(b), n, _dp(x), _dp(y), _dp(z),
+                                     layer.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(q),
+                                     len(targets), targets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     int(parts), _dp(out))
+    if rc:
+        raise ValueError(f"oracle_potential_ab failed ({rc})")
     return out
 
 

@@ -59,8 +59,12 @@ static int valid_side(int L, int layer, int side) {
 /* for the 2L unknowns; b = 1 is the response to (g1,g2) = (1,0) and b = 2   */
 /* the response to (0,1).  Gaussian elimination with partial pivoting.       */
 /* ------------------------------------------------------------------------ */
-int oracle_sigma(int L, const double* d, const double* eps, int lt, int ls,
-                 double k, double* out) {
+/* Densities for the general interface conditions a_{i} u_i = a_{i+1} u_{i+1}
+ * and b_i du_i/dz = b_{i+1} du_{i+1}/dz at z = d_i (the general conditions of
+ * App. A; a == NULL means a_i = 1, and b = eps gives the classic transmission
+ * conditions).  The same direct solve as the classic case, row by row. */
+int oracle_sigma_ab(int L, const double* d, const double* acoef, const double* eps, int lt,
+                    int ls, double k, double* out) {
   if (L < 1 || L > OR_MAXL || lt < 0 || lt > L || ls < 0 || ls > L) return -1;
   const int n = 2 * L;
   double A[2 * OR_MAXL][2 * OR_MAXL];
@@ -75,13 +79,14 @@ int oracle_sigma(int L, const double* d, const double* eps, int lt, int ls,
     const double ei = (i >= 1) ? exp(-k * (d[i - 1] - d[i])) : 0.0;
     const double ei1 = (i + 1 <= L - 1) ? exp(-k * (d[i] - d[i + 1])) : 0.0;
     const int rc = 2 * i, rf = 2 * i + 1;
-    /* continuity of u at z = d_i */
-    A[rc][C1(i)] += 1.0;
-    if (i >= 1) A[rc][C2(i)] += ei;
-    if (i + 1 <= L - 1) A[rc][C1(i + 1)] -= ei1;
-    A[rc][C2(i + 1)] -= 1.0;
-    if (ls == i) R[rc][0] -= 1.0;     /* g1 on the upper side */
-    if (ls == i + 1) R[rc][1] += 1.0; /* g2 on the lower side */
+    const double a0 = acoef ? acoef[i] : 1.0, a1 = acoef ? acoef[i + 1] : 1.0;
+    /* continuity of a u at z = d_i */
+    A[rc][C1(i)] += a0;
+    if (i >= 1) A[rc][C2(i)] += a0 * ei;
+    if (i + 1 <= L - 1) A[rc][C1(i + 1)] -= a1 * ei1;
+    A[rc][C2(i + 1)] -= a1;
+    if (ls == i) R[rc][0] -= a0;     /* g1 on the upper side */
+    if (ls == i + 1) R[rc][1] += a1; /* g2 on the lower side */
     /* continuity of eps du/dz at z = d_i (divided by -k) */
     A[rf][C1(i)] += eps[i];
     if (i >= 1) A[rf][C2(i)] -= eps[i] * ei;
@@ -128,6 +133,11 @@ int oracle_sigma(int L, const double* d, const double* eps, int lt, int ls,
 #undef C1
 #undef C2
   return 0;
+}
+
+int oracle_sigma(int L, const double* d, const double* eps, int lt, int ls,
+                 double k, double* out) {
+  return oracle_sigma_ab(L, d, NULL, eps, lt, ls, k, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -360,13 +370,13 @@ static double zeta_of(const double* d, int lt, int ls, int a, int b, double z,
  * themselves are stored as well, mat_out[ti * n + j] = the potential at
  * target ti of a unit charge at j (0 where no part applies); q may then be
  * NULL (unit charges). */
-static int potential_impl(int L, const double* d, const double* eps, int64_t n,
+static int potential_impl(int L, const double* d, const double* acoef, const double* eps, int64_t n,
                           const double* x, const double* y, const double* z,
                           const int32_t* layer, const double* q, int64_t nt,
                           const int64_t* targets, int method, int parts,
                           double* phi_out, double* mat_out) {
   if (L < 1 || L > OR_MAXL) return -1;
-  if (method == 1 && L != 2) return -1;
+  if (method == 1 && (L != 2 || acoef)) return -1;
   const int ncomp = (L + 1) * (L + 1) * 4;
   /* quadrature set-up: shared rule, sigma tabulated per component at nodes */
   rule_t rule = {0, NULL, NULL};
@@ -392,7 +402,7 @@ static int potential_impl(int L, const double* d, const double* eps, int64_t n,
       for (int lt = 0; lt <= L; ++lt)
         for (int ls = 0; ls <= L; ++ls) {
           double s4[4];
-          oracle_sigma(L, d, eps, lt, ls, rule.k[i], s4);
+          oracle_sigma_ab(L, d, acoef, eps, lt, ls, rule.k[i], s4);
           for (int c = 0; c < 4; ++c)
             sig[(size_t)((lt * (L + 1) + ls) * 4 + c) * rule.nn + i] = s4[c];
         }
@@ -506,7 +516,16 @@ int oracle_potential(int L, const double* d, const double* eps, int64_t n,
                      const int32_t* layer, const double* q, int64_t nt,
                      const int64_t* targets, int method, int parts,
                      double* phi_out) {
-  return potential_impl(L, d, eps, n, x, y, z, layer, q, nt, targets, method, parts, phi_out, NULL);
+  return potential_impl(L, d, NULL, eps, n, x, y, z, layer, q, nt, targets, method, parts, phi_out, NULL);
+}
+
+/* The direct sum for the general interface conditions (coefficients a, b;
+ * quadrature only). */
+int oracle_potential_ab(int L, const double* d, const double* acoef, const double* bcoef, int64_t n,
+                        const double* x, const double* y, const double* z,
+                        const int32_t* layer, const double* q, int64_t nt,
+                        const int64_t* targets, int parts, double* phi_out) {
+  return potential_impl(L, d, acoef, bcoef, n, x, y, z, layer, q, nt, targets, 0, parts, phi_out, NULL);
 }
 
 /* The dense matrix of eq. totalinteraction: G[ti * n + j] is the potential at
@@ -516,5 +535,5 @@ int oracle_matrix(int L, const double* d, const double* eps, int64_t n,
                   const double* x, const double* y, const double* z,
                   const int32_t* layer, int64_t nt, const int64_t* targets,
                   int method, int parts, double* phi_scratch, double* G) {
-  return potential_impl(L, d, eps, n, x, y, z, layer, NULL, nt, targets, method, parts, phi_scratch, G);
+  return potential_impl(L, d, NULL, eps, n, x, y, z, layer, NULL, nt, targets, method, parts, phi_scratch, G);
 }
