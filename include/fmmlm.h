@@ -141,6 +141,31 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
  * device first so that in-flight evaluations finish. */
 int fmm_layered_destroy(fmmlm_plan_t plan);
 
+/*
+ * A plan for the general interface conditions of App. A (eq.
+ * generalinterfacecond):
+ *
+ *   a_{l-1} u_{l-1} = a_l u_l,   b_{l-1} du_{l-1}/dz = b_l du_l/dz   at z = d_{l-1},
+ *
+ * for l = 1..L, with the same decay at z -> +-infinity; the classic
+ * transmission conditions are a_l = 1, b_l = eps_l.  Only the reaction
+ * densities change.  With v = a u in every layer the conditions become the
+ * classic ones for v with permittivities b / a and a source of strength a in
+ * the source layer, so each density is a_{l'} / a_l times the classic density
+ * for eps = b / a (target layer l, source layer l'), and every kernel of the
+ * classic plan serves unchanged.
+ *
+ *  a, b   host or device, n_interfaces + 1 coefficients each (top to bottom),
+ *         finite and > 0 (FMMLM_EEPS otherwise)
+ *  the other arguments are those of fmm_layered_plan; evaluation, solve and
+ *  destruction are the same calls.  opts.surrogate must be NULL (the learned
+ *  form is built for the classic conditions): FMMLM_EUNSUPPORTED otherwise.
+ */
+int fmm_layered_plan_general(int32_t n_interfaces, const double* z_interfaces, const double* a, const double* b,
+                             int64_t n, const double* x, const double* y, const double* z,
+                             const int32_t* layer_id, int32_t p, const fmmlm_opts* opts, void* hip_stream,
+                             fmmlm_plan_t* out);
+
 /* ---- iterative solve around the matvec ------------------------------------------ */
 /*
  * The paper's motivating application (Sec. 1): a dense system whose product is

@@ -277,6 +277,21 @@ Medium make_medium(int L, const double* d, const double* eps) {
   md.L = L;
   for (int i = 0; i < L; ++i) md.d[i] = d[i];
   for (int i = 0; i <= L; ++i) md.eps[i] = eps[i];
+  for (int i = 0; i <= kMaxL; ++i) md.acoef[i] = 1.0;
+  return md;
+}
+
+// The general interface conditions (coefficients a, b): eps = b / a, acoef = a.
+Medium make_medium_ab(int L, const double* d, const double* a, const double* b) {
+  Medium md;
+  std::memset(&md, 0, sizeof(md));
+  md.L = L;
+  for (int i = 0; i < L; ++i) md.d[i] = d[i];
+  for (int i = 0; i <= kMaxL; ++i) md.acoef[i] = 1.0;
+  for (int i = 0; i <= L; ++i) {
+    md.eps[i] = b[i] / a[i];
+    md.acoef[i] = a[i];
+  }
   return md;
 }
 
@@ -1376,9 +1391,13 @@ void fmmlm_default_opts(fmmlm_opts* o) {
   o->mac_d2 = 6;
 }
 
-int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const double* eps, int64_t n,
-                     const double* x, const double* y, const double* z, const int32_t* layer_id, int32_t p,
-                     const fmmlm_opts* opts, void* hip_stream, fmmlm_plan_t* out) {
+}  // extern "C"
+
+// The plan for the classic conditions (acoef null, eps the permittivities) or
+// for the general ones (acoef = a on the host, eps = b / a).
+static int plan_impl(int32_t n_interfaces, const double* z_interfaces, const double* eps, const double* acoef,
+                     int64_t n, const double* x, const double* y, const double* z, const int32_t* layer_id,
+                     int32_t p, const fmmlm_opts* opts, void* hip_stream, fmmlm_plan_t* out) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!out) return FMMLM_EINVAL;
   *out = nullptr;
@@ -1412,6 +1431,10 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
     set_last_error("the surrogate was trained for another medium");
     return FMMLM_EINVAL;
   }
+  if (o.surrogate && acoef) {
+    set_last_error("the learned form is built for the classic interface conditions");
+    return FMMLM_EUNSUPPORTED;
+  }
   if ((rc = fetch(x, n, X)) || (rc = fetch(y, n, Y)) || (rc = fetch(z, n, Z)) || (rc = fetch(layer_id, n, LAY)))
     return rc;
   const int L = n_interfaces;
@@ -1431,6 +1454,8 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   P->d = dv;
   P->eps = ev;
   P->medium = make_medium(L, dv.data(), ev.data());
+  if (acoef)
+    for (int i = 0; i <= L; ++i) P->medium.acoef[i] = acoef[i];
   P->N = n;
   P->p = p;
   P->nc = ncoef(p);
@@ -1463,6 +1488,32 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
   P->stats.plan_seconds = seconds_since(t0);
   *out = P;
   return FMMLM_OK;
+}
+
+extern "C" {
+
+int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const double* eps, int64_t n,
+                     const double* x, const double* y, const double* z, const int32_t* layer_id, int32_t p,
+                     const fmmlm_opts* opts, void* hip_stream, fmmlm_plan_t* out) {
+  return plan_impl(n_interfaces, z_interfaces, eps, nullptr, n, x, y, z, layer_id, p, opts, hip_stream, out);
+}
+
+int fmm_layered_plan_general(int32_t n_interfaces, const double* z_interfaces, const double* a, const double* b,
+                             int64_t n, const double* x, const double* y, const double* z, const int32_t* layer_id,
+                             int32_t p, const fmmlm_opts* opts, void* hip_stream, fmmlm_plan_t* out) {
+  if (!out) return FMMLM_EINVAL;
+  *out = nullptr;
+  if (!a || !b || n_interfaces < 1 || n_interfaces > kMaxL) return FMMLM_EINVAL;
+  std::vector<double> av, bv;
+  int rc;
+  if ((rc = fetch(a, n_interfaces + 1, av)) || (rc = fetch(b, n_interfaces + 1, bv))) return rc;
+  std::vector<double> ev(n_interfaces + 1);
+  for (int i = 0; i <= n_interfaces; ++i) {
+    if (!std::isfinite(av[i]) || !(av[i] > 0.0) || !std::isfinite(bv[i]) || !(bv[i] > 0.0)) return FMMLM_EEPS;
+    ev[i] = bv[i] / av[i];
+  }
+  return plan_impl(n_interfaces, z_interfaces, ev.data(), av.data(), n, x, y, z, layer_id, p, opts, hip_stream,
+                   out);
 }
 
 int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t ldq, double* phi, int64_t ldphi,

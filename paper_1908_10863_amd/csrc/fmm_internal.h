@@ -52,10 +52,16 @@ __device__ inline cplx cexp_dev(cplx a) {
 }
 
 // ---- layered medium (passed by value to kernels) ------------------------------
+// General interface conditions a_{i} u_i = a_{i+1} u_{i+1}, b_i u_i' =
+// b_{i+1} u_{i+1}' are held as eps = b / a and acoef = a: with v = a u they are
+// the classic conditions for v with permittivities b / a and a source of
+// strength a in the source layer, so every density is a_ls / a_lt times the
+// classic one for eps = b / a (classic: acoef = 1).
 struct Medium {
   int L;                      // interfaces; 0 means sigma == 1 (test medium)
   double d[kMaxL];            // interface heights, decreasing
-  double eps[kMaxL + 1];      // permittivities, top to bottom
+  double eps[kMaxL + 1];      // permittivities (b / a), top to bottom
+  double acoef[kMaxL + 1];    // the a coefficients (1 for the classic conditions)
 };
 
 // coefficient index of (n, m), 0 <= m <= n

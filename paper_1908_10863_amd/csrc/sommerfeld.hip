@@ -45,10 +45,10 @@ __device__ void local_coeffs(const Medium& md, Scatter& sc) {
   }
 }
 
-// sigma^{ab}_{lt,ls}(k); k complex with Re k >= 0.
-__device__ cplx density(const Medium& md, const Scatter& sc, int lt, int ls, int a, int b, cplx k) {
+// sigma^{ab}_{lt,ls}(k) of the classic conditions for md.eps; k complex with
+// Re k >= 0.
+__device__ cplx density_classic(const Medium& md, const Scatter& sc, int lt, int ls, int a, int b, cplx k) {
   const int L = md.L;
-  if (L == 0) return cmk(1.0, 0.0);
   // propagation factor across finite layer i (1 <= i <= L-1): e_i = exp(-k D_i)
   cplx e[kMaxL + 1], e2[kMaxL + 1];
   for (int i = 0; i <= L; ++i) {
@@ -116,6 +116,13 @@ __device__ cplx density(const Medium& md, const Scatter& sc, int lt, int ls, int
   }
   if (a == 2) return s2;
   return (lt <= L - 1) ? Gdn[lt] * (e[lt] * s2) : zero;
+}
+
+// sigma^{ab}_{lt,ls}(k) of the medium's interface conditions (factor a_ls / a_lt,
+// exactly 1 for the classic conditions)
+__device__ cplx density(const Medium& md, const Scatter& sc, int lt, int ls, int a, int b, cplx k) {
+  if (md.L == 0) return cmk(1.0, 0.0);
+  return (md.acoef[ls] / md.acoef[lt]) * density_classic(md, sc, lt, ls, a, b, k);
 }
 
 // ---------------------------------------------------------------- Bessel K_0, K_1
@@ -650,8 +657,7 @@ double zeta_inf(const Medium& md, int lt, int ls, int a, int b) {
 // reflection and transmission coefficients met along the shortest ray path of
 // zeta_inf (every other path crosses some finite layer twice more, so
 // sigma(k) e^{k zinf} - sinf = O(e^{-2 k dmin})).
-double sigma_inf(const Medium& md, int lt, int ls, int a, int b) {
-  if (md.L == 0) return 1.0;
+static double sigma_inf_classic(const Medium& md, int lt, int ls, int a, int b) {
   auto rdn = [&](int i) { return (md.eps[i] - md.eps[i + 1]) / (md.eps[i] + md.eps[i + 1]); };
   auto rup = [&](int i) { return (md.eps[i + 1] - md.eps[i]) / (md.eps[i] + md.eps[i + 1]); };
   auto tdn = [&](int i) { return 2.0 * md.eps[i] / (md.eps[i] + md.eps[i + 1]); };
@@ -668,6 +674,11 @@ double sigma_inf(const Medium& md, int lt, int ls, int a, int b) {
   double s = (b == 1) ? 1.0 : rup(ls - 1);
   for (int i = ls + 1; i <= lt; ++i) s *= tdn(i - 1);
   return (a == 2) ? s : rdn(lt) * s;
+}
+
+double sigma_inf(const Medium& md, int lt, int ls, int a, int b) {
+  if (md.L == 0) return 1.0;
+  return (md.acoef[ls] / md.acoef[lt]) * sigma_inf_classic(md, lt, ls, a, b);
 }
 
 int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,

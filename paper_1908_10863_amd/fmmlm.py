@@ -87,7 +87,8 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_create_for_plan", "fmm_layered_surrogate_train",
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
-           "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve"]
+           "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve",
+           "fmm_layered_plan_general"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -115,6 +116,9 @@ def lib():
     L.fmm_layered_eval.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                    ctypes.c_uint32, vp]
     L.fmm_layered_eval.restype = ctypes.c_int
+    L.fmm_layered_plan_general.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp,
+                                           ctypes.c_int32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.fmm_layered_plan_general.restype = ctypes.c_int
     L.fmm_layered_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
     L.fmm_layered_solve.restype = ctypes.c_int
     L.fmm_layered_destroy.argtypes = [vp]
@@ -192,10 +196,14 @@ def _stream_handle(stream):
 
 
 class Plan:
-    """fmm_layered_plan over host geometry; eval on torch CUDA tensors."""
+    """fmm_layered_plan over host geometry; eval on torch CUDA tensors.
+
+    interface_a: the a coefficients of the general interface conditions
+    (fmm_layered_plan_general); eps then holds the b coefficients."""
 
     def __init__(self, d, eps, x, y, z, layer, p, leaf_cap=64, precision=FMMLM_FP64,
-                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None, surrogate=None, graph=False):
+                 fp64_top_levels=3, max_rhs=1, mac_d2=None, stream=None, surrogate=None, graph=False,
+                 interface_a=None):
         self.d = _host(d, np.float64)
         self.eps = _host(eps, np.float64)
         x, y, z = _host(x, np.float64), _host(y, np.float64), _host(z, np.float64)
@@ -213,9 +221,17 @@ class Plan:
             o.surrogate = surrogate._h
         o.graph = 1 if graph else 0
         h = ctypes.c_void_p()
-        rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
-                                    _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),
-                                    _stream_handle(stream), ctypes.byref(h))
+        if interface_a is None:
+            rc = lib().fmm_layered_plan(len(self.d), _ptr(self.d), _ptr(self.eps), self.n, _ptr(x),
+                                        _ptr(y), _ptr(z), _ptr(layer), p, ctypes.byref(o),
+                                        _stream_handle(stream), ctypes.byref(h))
+        else:
+            self.a = _host(interface_a, np.float64)
+            if len(self.a) != len(self.eps):
+                raise ValueError("interface_a needs one coefficient per layer")
+            rc = lib().fmm_layered_plan_general(len(self.d), _ptr(self.d), _ptr(self.a), _ptr(self.eps),
+                                                self.n, _ptr(x), _ptr(y), _ptr(z), _ptr(layer), p,
+                                                ctypes.byref(o), _stream_handle(stream), ctypes.byref(h))
         check(rc)
         self._h = h
         self.p = p

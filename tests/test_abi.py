@@ -115,6 +115,28 @@ def test_eval_rejects_null_plan(L):
     assert L.fmm_layered_eval(None, 1, None, 1, None, 1, 3, None) == -1
 
 
+def test_plan_general_validates_coefficients(L):
+    x, y, z, lay = (np.asarray(v, t) for v, t in (([0.1, 0.2], np.float64), ([0.0, 0.1], np.float64),
+                                                   ([0.5, -0.5], np.float64), ([0, 1], np.int32)))
+    d = np.array([0.0, -1.0])
+
+    def rc_of(a, b):
+        a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        h = ctypes.c_void_p()
+        return L.fmm_layered_plan_general(2, ctypes.c_void_p(d.ctypes.data), ctypes.c_void_p(a.ctypes.data),
+                                          ctypes.c_void_p(b.ctypes.data), 2, ctypes.c_void_p(x.ctypes.data),
+                                          ctypes.c_void_p(y.ctypes.data), ctypes.c_void_p(z.ctypes.data),
+                                          ctypes.c_void_p(lay.ctypes.data), 4, None, None, ctypes.byref(h)), h
+
+    for a, b in (([1.0, -1.0, 1.0], [1.0, 2.0, 3.0]), ([1.0, 1.0, 1.0], [1.0, 0.0, 3.0]),
+                 ([1.0, float("nan"), 1.0], [1.0, 2.0, 3.0]), ([1.0, 1.0, 1.0], [float("inf"), 2.0, 3.0])):
+        rc, h = rc_of(a, b)
+        assert rc == -3 and not h.value
+    h = ctypes.c_void_p()
+    assert L.fmm_layered_plan_general(2, None, None, None, 2, None, None, None, None, 4, None, None,
+                                      ctypes.byref(h)) == -1
+
+
 def test_solve_rejects_null_plan(L):
     from paper_1908_10863_amd import fmmlm
     info = fmmlm.SolveInfo()

@@ -1,0 +1,87 @@
+"""General interface conditions (fmm_layered_plan_general) against the oracle's
+direct solve of the general interface system.
+
+* a = 1, b = eps: the same evaluation as the classic plan, bit for bit.
+* Three layers, a = (1, 0.5, 2), b = (1, 3, 6); FP64 form p = 12, mac 6,
+  N = 1500: rel L2 <= 1e-6 on 60 targets (the oracle's quadrature sum).
+* Four layers, seeded a, b; FP32 form p = 10, mac 4, N = 4000: rel L2 <= 2e-5
+  on 40 targets.
+* The learned form is refused for a general plan.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1908_10863_amd import fmmlm
+    fmmlm.lib()
+    return fmmlm
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_classic_coefficients_give_the_classic_plan(dev, F):
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(0)
+    q = torch.tensor(w["q"][0], device=dev)
+    kw = dict(p=8, leaf_cap=40)
+    pc = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], **kw)
+    pg = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], interface_a=[1.0] * len(w["eps"]), **kw)
+    a, b = pc.eval(q), pg.eval(q)
+    pc.close()
+    pg.close()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["3layer_fp64", "4layer_fp32"])
+def test_general_conditions_vs_oracle(dev, F, oracle_mod, case):
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    if case == "3layer_fp64":
+        w = W.config(0, n=1500, seed=21)
+        a, b = np.array([1.0, 0.5, 2.0]), np.array([1.0, 3.0, 6.0])
+        kw = dict(p=12, leaf_cap=40, precision=0, mac_d2=6)
+        nt, tol = 60, 1e-6
+    else:
+        w = W.config(3, n=4000, seed=22)
+        rng = np.random.default_rng(23)
+        a, b = rng.uniform(0.4, 2.5, 4), rng.uniform(0.8, 10.0, 4)
+        kw = dict(p=10, leaf_cap=64, precision=1, mac_d2=4)
+        nt, tol = 40, 2e-5
+    _say(f"general conditions {case}: a={np.round(a, 3)} b={np.round(b, 3)}")
+    pl = F.Plan(w["d"], b, w["x"], w["y"], w["z"], w["layer"], interface_a=a, **kw)
+    phi = pl.eval(torch.tensor(w["q"][0], device=dev)).cpu().numpy()
+    pl.close()
+    t = np.sort(np.random.default_rng(24).choice(len(w["x"]), nt, replace=False))
+    ref = oracle_mod.potential_ab(w["d"], a, b, w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=t)
+    e = relerr(phi[t], ref)
+    _say(f"  rel L2 {e:.2e}")
+    assert e <= tol
+
+
+def test_learned_form_refused(dev, F):
+    s = F.Surrogate([0.0, -1.0], [1.0, 5.0, 2.0], p=4, rho_max=1.5, zeta_max=2.2, seed=3)
+    with pytest.raises(Exception):
+        F.Plan([0.0, -1.0], [1.0, 5.0, 2.0], [0.1, 0.2], [0.0, 0.1], [0.5, -0.5], [0, 1], p=4,
+               surrogate=s, interface_a=[1.0, 1.0, 1.0])
