@@ -212,6 +212,7 @@ extern "C" int fmm_layered_solve(fmmlm_plan_t plan, const double* diag, const do
       gm_combine_kernel<<<nb, kSolveThreads, 0, st>>>(n, k + 1, V(0), ldv, h2, -1.0, V(k + 1));
       dots(V(k + 1), 1, V(k + 1), nrm2);
       gm_scale_kernel<<<nb, kSolveThreads, 0, st>>>(n, nrm2, V(k + 1));
+      FMM_HIP_TRY(hipGetLastError());
       FMM_HIP_TRY(hipMemcpyAsync(hh.data(), wk.small, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, st));
       FMM_HIP_TRY(hipStreamSynchronize(st));
       for (int j = 0; j <= k; ++j) col[j] = hh[j] + hh[(m + 2) + j];
@@ -252,6 +253,7 @@ extern "C" int fmm_layered_solve(fmmlm_plan_t plan, const double* diag, const do
     if (int rc = read_scalar(nrm2, &beta2)) return rc;
     relres = std::sqrt(beta2) / bn;
   }
+  FMM_HIP_TRY(hipGetLastError());
   FMM_HIP_TRY(hipStreamSynchronize(st));
   info->relres = relres;
   info->converged = relres <= o.tol ? 1 : 0;
