@@ -273,7 +273,12 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
     // w = e^{-i eta z} (sigma(i eta) - sinf e^{-i eta zinf})
     pn.kmax = (2.0 * nmax + 50.0) / rho;
     double hmax = 2.0 / rho;
-    const double osc = z + c.zinf + 4.0 * max_thickness(md);
+    // sigma(i eta) does not decay along the imaginary axis: a wave reflected
+    // through the whole stack oscillates like e^{-2 i eta (stack thickness)},
+    // so the panels resolve two round trips through the stack (for three
+    // layers the stack is the one finite layer)
+    const double stack = md.L >= 2 ? md.d[0] - md.d[md.L - 1] : 0.0;
+    const double osc = z + c.zinf + 4.0 * fmax(max_thickness(md), stack);
     if (3.14159265358979 / osc < hmax) hmax = 3.14159265358979 / osc;
     pn.hmax = hmax;
     double k0 = 0.0, h = pn.h0;
