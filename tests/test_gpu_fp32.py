@@ -58,6 +58,23 @@ def test_fp32_small_vs_oracle(dev, F, oracle_mod, mac):
     assert e32 <= e64 + 2e-6
 
 
+def test_fp32_six_region_medium(dev, F, oracle_mod):
+    """The six-region medium (five interfaces, about 100 reaction components, the
+    FP32 form's sparse top levels and reaction chunks all in play) against the
+    quadrature direct sum on 48 targets: FP32 form <= 1e-5, FP64 form <= 1e-6."""
+    from paper_1908_10863_amd import workloads as W
+    _say("fp32 six regions")
+    w = W.config(4, n=12000, seed=44)
+    t = np.sort(np.random.default_rng(45).choice(12000, 48, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=t,
+                               method="quad")
+    e32 = relerr(_phi(F, w, dev, F.FMMLM_FP32_COMPENSATED, 10, 64, 4)[t], ref)
+    e64 = relerr(_phi(F, w, dev, F.FMMLM_FP64, 10, 64, 6)[t], ref)
+    _say(f"  fp32 {e32:.3e} fp64 {e64:.3e}")
+    assert e32 <= 1e-5
+    assert e64 <= 1e-6
+
+
 def test_fp32_full_size_sampled(dev, F, oracle_mod):
     """Workload 3 at full size (N = 1048576, p = 10): 64 sampled targets against the
     direct sum over all sources."""
