@@ -58,6 +58,20 @@ def test_fp32_small_vs_oracle(dev, F, oracle_mod, mac):
     assert e32 <= e64 + 2e-6
 
 
+def test_fp32_across_orders(dev, F, oracle_mod):
+    """p = 4, 8, 14, 16 (other padded operator sizes than p = 10's): the FP32 form
+    follows the FP64 form's truncation error down to its own rounding floor
+    (about 3e-7)."""
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(0, n=3000)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    for p in (4, 8, 14, 16):
+        e32 = relerr(_phi(F, w, dev, F.FMMLM_FP32_COMPENSATED, p, 32, 6), ref)
+        e64 = relerr(_phi(F, w, dev, F.FMMLM_FP64, p, 32, 6), ref)
+        _say(f"  p {p}: fp32 {e32:.2e} fp64 {e64:.2e}")
+        assert e32 <= max(1.2 * e64, 5e-7)
+
+
 def test_fp32_six_region_medium(dev, F, oracle_mod):
     """The six-region medium (five interfaces, about 100 reaction components, the
     FP32 form's sparse top levels and reaction chunks all in play) against the
