@@ -72,6 +72,25 @@ def test_fp32_across_orders(dev, F, oracle_mod):
         assert e32 <= max(1.2 * e64, 5e-7)
 
 
+def test_fp32_four_million_points(dev, F, oracle_mod):
+    """Four times the benchmark's size (N = 4194304, FP32 form, the benchmark's p,
+    MAC and leaf cap): 24 sampled targets against the direct sum over all sources."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    n = 4194304
+    _say(f"fp32 N={n}")
+    w = W.config(2, n=n, seed=51)
+    pl = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=192,
+                precision=F.FMMLM_FP32_COMPENSATED, mac_d2=4)
+    phi = pl.eval(torch.tensor(w["q"][0], device=dev)).cpu().numpy()
+    pl.close()
+    t = np.sort(np.random.default_rng(52).choice(n, 24, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=t)
+    e = relerr(phi[t], ref)
+    _say(f"  rel L2 {e:.2e}")
+    assert e <= 1e-5
+
+
 def test_fp32_six_region_medium(dev, F, oracle_mod):
     """The six-region medium (five interfaces, about 100 reaction components, the
     FP32 form's sparse top levels and reaction chunks all in play) against the
