@@ -259,6 +259,28 @@ def test_contour_form_resolves_the_whole_stack(dev, F, oracle_mod):
             assert abs(g - o) <= 1e-7 * abs(o), (a, b, zeta, rho, g, o)
 
 
+def test_points_hugging_an_interface(dev, F, oracle_mod):
+    """Two thirds of the points within 1e-4..2e-3 of the top interface, on both
+    sides (tiny zeta for the reaction self and near terms), three layers: FP64 p = 12
+    <= 1e-7 and the FP32 form <= 1e-5 against the image-series direct sum."""
+    import torch
+    d, eps = D3, E3
+    rng = np.random.default_rng(61)
+    n = 3000
+    lay = np.repeat([0, 1, 2], n // 3).astype(np.int32)
+    z = np.where(lay == 0, rng.uniform(1e-4, 2e-3, n),
+                 np.where(lay == 1, rng.uniform(-2e-3, -1e-4, n), rng.uniform(-1.5, -1.1, n)))
+    x, y, q = rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), rng.uniform(-1, 1, n)
+    ref = oracle_mod.potential(d, eps, x, y, z, lay, q, method="image3")
+    for prec, p, mac, tol in [(0, 12, 6, 1e-7), (1, 10, 4, 1e-5)]:
+        pl = F.Plan(d, eps, x, y, z, lay, p=p, leaf_cap=40, precision=prec, mac_d2=mac)
+        phi = pl.eval(torch.tensor(q, device=dev)).cpu().numpy()
+        pl.close()
+        e = relerr(phi, ref)
+        _say(f"  hugging the interface, precision {prec}: {e:.2e}")
+        assert e < tol
+
+
 def test_high_contrast_medium(dev, F, oracle_mod):
     """eps = (1, 80, 1): reflections of magnitude 0.975 give the density sharp
     resonances along the imaginary axis.  The contour form's integrals stay within
