@@ -284,17 +284,22 @@ typedef struct {
                                   the free P2P leaves launched at the fork and the rest after the
                                   main M2L launch ... */
   int32_t p2p_split_pct;       /*   ... and the percentage kept (the fastest) */
-  int32_t reserved_stats3;
+  int32_t batch_min_rhs;       /* batched passes narrower than this run vector by vector
+                                  (timed at plan time: one batched pass of max_rhs vectors
+                                  against one single-vector evaluation) */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);
 
 /* Overrides the autotuner's choices (tests, benchmarks): m2l_variant selects the
  * FP32 M2L tile shape (0..5, see m2l_variant_ms), batch_variant the batched FP32
- * M2L variant (0..9, see batch_variant_ms); -1 leaves a choice unchanged.
- * FMMLM_EINVAL for a value out of range or a variant the plan does not have
- * ((p+1)^2 > 128 has one shape: 0, or 0 and 1 for the batched M2L). */
-int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant);
+ * M2L variant (0..9, see batch_variant_ms), batch_min_rhs the narrowest pass that
+ * runs batched (2..65, see fmmlm_stats.batch_min_rhs; 65 runs every vector on its
+ * own); -1 leaves a choice unchanged.  FMMLM_EINVAL for a value out of range or a
+ * variant the plan does not have ((p+1)^2 > 128 has one shape: 0, or 0 and 1 for
+ * the batched M2L). */
+int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant,
+                                  int32_t batch_min_rhs);
 
 /*
  * Tree t (0 <= t < n_trees) of a plan.  Trees are ordered by layer, then side

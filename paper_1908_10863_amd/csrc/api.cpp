@@ -368,6 +368,59 @@ int surrogate_check(fmmlm_plan_s* P, const std::vector<CompInfo>& comps, const s
   return FMMLM_OK;
 }
 
+// A batched pass costs about the same at any width (its kernels run 64 lanes a
+// vector block), so narrow passes are slower than evaluating their vectors one
+// by one.  Time one single-vector evaluation and one batched pass of gmax
+// vectors (zero charges; best of three after a warm-up) and set the width from
+// which a batched pass pays.
+static int tune_batch_width(fmmlm_plan_s* P, hipStream_t st) {
+  P->batch_min = 2;
+  P->stats.batch_min_rhs = 2;
+  if (P->gmax < 2) return FMMLM_OK;
+  const size_t bytes = (size_t)P->N * (size_t)P->gmax * sizeof(double);
+  double *q = nullptr, *phi = nullptr;
+  FMM_HIP_TRY(hipMalloc(&q, bytes));
+  if (hipMalloc(&phi, bytes) != hipSuccess) {
+    (void)hipFree(q);
+    return FMMLM_ENOMEM;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = FMMLM_OK;
+  if (hipMemsetAsync(q, 0, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    rc = FMMLM_EDEVICE;
+  auto best_ms = [&](bool batched) -> double {
+    double tmin = 1e300;
+    for (int rep = 0; rep < 4 && rc == FMMLM_OK; ++rep) {
+      (void)hipEventRecord(e0, st);
+      rc = batched ? gpu_eval_batch(P, P->gmax, q, P->N, phi, P->N, FMMLM_FREE | FMMLM_REACTION, st, nullptr)
+                   : gpu_eval_one(P, q, phi, FMMLM_FREE | FMMLM_REACTION, st, nullptr);
+      (void)hipEventRecord(e1, st);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = FMMLM_EDEVICE;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tmin = std::min(tmin, (double)ms);
+    }
+    return tmin;
+  };
+  const double t1 = best_ms(false);
+  const double tb = best_ms(true);
+  if (rc == FMMLM_OK && t1 > 0.0 && tb < 1e300) {
+    const double w = std::ceil(tb / t1);
+    P->batch_min = (int)std::max(2.0, std::min(w, (double)P->gmax + 1.0));
+    P->stats.batch_min_rhs = P->batch_min;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(q);
+  (void)hipFree(phi);
+  return rc;
+}
+
 int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<double>& Y,
                const std::vector<double>& Z, const std::vector<int32_t>& LAY, hipStream_t st) {
   const int L = P->L;
@@ -1239,6 +1292,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   FMM_HIP_TRY(hipStreamSynchronize(st));
   if (P->fp32 && (rc = gpu_tune_eval(P, st))) return rc;
   FMM_HIP_TRY(hipStreamSynchronize(st));
+  if ((rc = tune_batch_width(P, st))) return rc;
   return FMMLM_OK;
 }
 
@@ -1524,13 +1578,25 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   if (parts == 0 || (parts & ~(FMMLM_FREE | FMMLM_REACTION))) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   auto launch = [&]() -> int {
-    if (nrhs == 1) {
-      hipEvent_t* ev = nullptr;
-      if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
-      return gpu_eval_one(plan, q, phi, parts, st, ev);
+    if (nrhs < plan->batch_min) {
+      for (int r = 0; r < nrhs; ++r) {
+        hipEvent_t* ev = nullptr;
+        if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
+        if (int rc = gpu_eval_one(plan, q + (int64_t)r * ldq, phi + (int64_t)r * ldphi, parts, st, ev)) return rc;
+      }
+      return FMMLM_OK;
     }
     for (int r0 = 0; r0 < nrhs; r0 += plan->gmax) {
       const int g = std::min(plan->gmax, nrhs - r0);
+      if (g < plan->batch_min) {
+        // a narrow last pass: vector by vector
+        for (int r = r0; r < r0 + g; ++r) {
+          hipEvent_t* ev = nullptr;
+          if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
+          if (int rc = gpu_eval_one(plan, q + (int64_t)r * ldq, phi + (int64_t)r * ldphi, parts, st, ev)) return rc;
+        }
+        continue;
+      }
       hipEvent_t* ev = nullptr;
       if (plan->prof_used < plan->prof_cap) ev = &plan->prof_ev[(size_t)plan->prof_used++ * (FMMLM_NSTAGES + 1)];
       int rc = gpu_eval_batch(plan, g, q + (int64_t)r0 * ldq, ldq, phi + (int64_t)r0 * ldphi, ldphi, parts, st, ev);
@@ -1572,13 +1638,16 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   return rc;
 }
 
-int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant) {
+int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant,
+                                  int32_t batch_min_rhs) {
   if (!plan) return FMMLM_EINVAL;
   const int nm = plan->mrt == 4 ? kM2LVariants : 1;
   const int nb = plan->mrt == 4 ? 2 * kBatchShapes : 2;
   if (m2l_variant < -1 || m2l_variant >= nm || batch_variant < -1 || batch_variant >= nb) return FMMLM_EINVAL;
+  if (batch_min_rhs != -1 && (batch_min_rhs < 2 || batch_min_rhs > 65)) return FMMLM_EINVAL;
   if (m2l_variant >= 0) plan->m2l_variant = plan->stats.m2l_variant = m2l_variant;
   if (batch_variant >= 0) plan->batch_variant = plan->stats.batch_variant = batch_variant;
+  if (batch_min_rhs >= 0) plan->batch_min = plan->stats.batch_min_rhs = batch_min_rhs;
   drop_graph(plan);  // a captured evaluation holds the old launches
   return FMMLM_OK;
 }

@@ -180,6 +180,7 @@ struct fmmlm_plan_s {
   // batched form (opts.max_rhs > 1): expansions, charges and potentials of up
   // to G = min(max_rhs, 64) vectors; M2L one block per target box
   int gmax = 1;
+  int batch_min = 2;               // batched passes narrower than this run vector by vector
   int64_t nbbox = 0, bbox_split = 0;
   int32_t* bbox = nullptr;         // target boxes with M2L entries, level order
   // batched M2M / L2L through the batched FP64 GEMM: per box CSR of its

@@ -76,7 +76,7 @@ class Stats(ctypes.Structure):
                 ("m2l_variant_ms", ctypes.c_double * 6), ("batch_variant", ctypes.c_int32),
                 ("reserved_stats2", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10),
                 ("m2l_eval_ms", ctypes.c_double * 6), ("p2p_split_ms", ctypes.c_double * 5),
-                ("p2p_split_pct", ctypes.c_int32), ("reserved_stats3", ctypes.c_int32)]
+                ("p2p_split_pct", ctypes.c_int32), ("batch_min_rhs", ctypes.c_int32)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",
@@ -164,7 +164,7 @@ def lib():
     L.fmm_layered_surrogate_eval.restype = ctypes.c_int
     L.fmm_layered_surrogate_samples.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp]
     L.fmm_layered_surrogate_samples.restype = ctypes.c_int
-    L.fmm_layered_plan_set_variants.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.fmm_layered_plan_set_variants.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.fmm_layered_plan_set_variants.restype = ctypes.c_int
     L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
     L.fmm_layered_profile_begin.restype = ctypes.c_int
@@ -270,9 +270,9 @@ class Plan:
                                       ctypes.byref(o), _stream_handle(stream), ctypes.byref(info)))
         return x, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
-    def set_variants(self, m2l=-1, batch=-1):
-        """Override the autotuner's kernel variants (see fmm_layered_plan_set_variants)."""
-        check(lib().fmm_layered_plan_set_variants(self._h, m2l, batch))
+    def set_variants(self, m2l=-1, batch=-1, batch_min=-1):
+        """Override the autotuner's choices (see fmm_layered_plan_set_variants)."""
+        check(lib().fmm_layered_plan_set_variants(self._h, m2l, batch, batch_min))
 
     def stats(self) -> dict:
         s = Stats()

@@ -42,6 +42,7 @@ def test_batched_equals_single(dev, F, precision):
     w = W.config(3, n=3000)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=8, leaf_cap=40,
                   precision=precision, max_rhs=70)
+    plan.set_variants(batch_min=2)  # batched kernels for every pass (the tuner may prefer single ones)
     rng = np.random.default_rng(4)
     Q = torch.tensor(rng.uniform(-1, 1, (70, 3000)), dtype=torch.float64, device=dev)
     both = plan.eval(Q).cpu().numpy()
@@ -55,6 +56,36 @@ def test_batched_equals_single(dev, F, precision):
     plan.close()
 
 
+def test_narrow_batches_run_vector_by_vector(dev, F):
+    """The plan times one batched pass against one single-vector evaluation and runs
+    narrower passes vector by vector: a call narrower than the tuned width equals
+    single-vector evaluations bit for bit, and with the width forced to 2 the
+    batched kernels give the same values within FP32 rounding."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(0, n=3000, seed=12)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=32,
+                  precision=F.FMMLM_FP32_COMPENSATED, max_rhs=64, mac_d2=4)
+    bm = plan.stats()["batch_min_rhs"]
+    _say(f"  tuned batch width {bm}")
+    assert 2 <= bm <= 65
+    Q = torch.tensor(np.random.default_rng(13).uniform(-1, 1, (4, 3000)), dtype=torch.float64, device=dev)
+    one = [plan.eval(Q[r].contiguous()) for r in range(4)]
+    if bm > 4:
+        four = plan.eval(Q)
+        for r in range(4):
+            assert torch.equal(four[r], one[r])
+    plan.set_variants(batch_min=2)
+    assert plan.stats()["batch_min_rhs"] == 2
+    four = plan.eval(Q).cpu().numpy()
+    for r in range(4):
+        assert relerr(four[r], one[r].cpu().numpy()) < 2e-6
+    for bad in (1, 66):
+        with pytest.raises(Exception):
+            plan.set_variants(batch_min=bad)
+    plan.close()
+
+
 def test_batched_fp32_vs_oracle_small(dev, F, oracle_mod):
     import torch
     from paper_1908_10863_amd import workloads as W
@@ -62,6 +93,7 @@ def test_batched_fp32_vs_oracle_small(dev, F, oracle_mod):
     w = W.config(3, n=2000)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=32,
                   precision=F.FMMLM_FP32_COMPENSATED, max_rhs=64, mac_d2=4)
+    plan.set_variants(batch_min=2)
     Q = torch.tensor(w["q"], dtype=torch.float64, device=dev)
     phi = plan.eval(Q).cpu().numpy()
     plan.close()
@@ -86,6 +118,7 @@ def test_batched_full_size_sampled(dev, F, oracle_mod):
     Q = torch.tensor(w["q"], dtype=torch.float64, device=dev)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=128,
                   precision=F.FMMLM_FP32_COMPENSATED, max_rhs=64, mac_d2=4)
+    plan.set_variants(batch_min=2)
     phi = plan.eval(Q).cpu().numpy()
     plan.close()
     rng = np.random.default_rng(77)

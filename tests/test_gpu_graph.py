@@ -38,6 +38,7 @@ def test_graph_replays_equal_eager(F, precision, nrhs):
     w = W.config(0, n=1200)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=8, leaf_cap=40,
                   precision=precision, max_rhs=nrhs, graph=True)
+    plan.set_variants(batch_min=2)
     side = torch.cuda.Stream()
     rng = np.random.default_rng(5)
     shape = (nrhs, 1200) if nrhs > 1 else (1200,)

@@ -399,6 +399,7 @@ def test_multiple_rhs_and_determinism(dev, F):
     _say("multi rhs")
     w = W.config(0, n=600)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=6, leaf_cap=30, max_rhs=3)
+    plan.set_variants(batch_min=2)  # the batched pass, whatever the tuner measured
     rng = np.random.default_rng(1)
     Q = torch.tensor(rng.uniform(-1, 1, (3, 600)), dtype=torch.float64, device=dev)
     both = plan.eval(Q).cpu().numpy()

@@ -59,6 +59,7 @@ def test_batched_m2l_variants(F, oracle_mod):
     g = 64
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=24, precision=1,
                   mac_d2=4, max_rhs=g)
+    plan.set_variants(batch_min=2)
     st = plan.stats()
     _say(f"batched M2L tuned variant {st['batch_variant']} times "
          f"{[round(t, 4) for t in st['batch_variant_ms']]}")
