@@ -233,10 +233,11 @@ __device__ void initial_values(const Medium& md, const Scatter& sc, const CompIn
   pn.h0 = 1e-3 * small;
   if (!contour) {
     // real axis: J_m(k rho) (kS)^n e^{-kz} (sigma(k) - sinf e^{-k zinf})
+    // panel widths are inverse lengths: the remainder decays on 1/zq (and
+    // zq >= 2 dmin, so thin layers shrink it), J_m(k rho) oscillates on pi/rho
     pn.kmax = (2.0 * nmax + 50.0) / zq;
     double hmax = 2.0 / zq;
     if (rho > 0.0 && 3.14159265358979 / rho < hmax) hmax = 3.14159265358979 / rho;
-    if (2.5 * dmin < hmax) hmax = 2.5 * dmin;
     pn.hmax = hmax;
     double k0 = 0.0, h = pn.h0;
     int zoom = kZoom + 1;  // first panel [0, h0] split geometrically towards 0

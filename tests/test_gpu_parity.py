@@ -281,6 +281,33 @@ def test_points_hugging_an_interface(dev, F, oracle_mod):
         assert e < tol
 
 
+def test_scale_and_translation_invariance(dev, F):
+    """Lengths scaled by s give potentials scaled by 1/s, and a lateral shift
+    changes nothing (no absolute length hides in the plan: an inverse-length
+    panel bound once written as a length made a 1e-3 scale take effectively
+    forever).  FP64 form p = 12 and the FP32 form."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(0, n=3000, seed=71)
+    q = torch.tensor(w["q"][0], device=dev)
+
+    def run(d, x, y, z, prec):
+        kw = dict(p=12, leaf_cap=40, mac_d2=6) if prec == 0 else dict(p=10, leaf_cap=40, mac_d2=4, precision=1)
+        pl = F.Plan(d, w["eps"], x, y, z, w["layer"], **kw)
+        phi = pl.eval(q).cpu().numpy()
+        pl.close()
+        return phi
+
+    for prec, tol_s, tol_t in [(0, 1e-12, 1e-9), (1, 1e-6, 1e-7)]:
+        base = run(w["d"], w["x"], w["y"], w["z"], prec)
+        for s in (1e-3, 1e3):
+            _say(f"  precision {prec}, lengths x {s:g}")
+            phi = run([v * s for v in w["d"]], w["x"] * s, w["y"] * s, w["z"] * s, prec) * s
+            assert relerr(phi, base) < tol_s, (prec, s)
+        phi = run(w["d"], w["x"] + 1e4, w["y"] - 1e4, w["z"], prec)
+        assert relerr(phi, base) < tol_t, prec
+
+
 def test_high_contrast_medium(dev, F, oracle_mod):
     """eps = (1, 80, 1): reflections of magnitude 0.975 give the density sharp
     resonances along the imaginary axis.  The contour form's integrals stay within
