@@ -308,6 +308,30 @@ def test_scale_and_translation_invariance(dev, F):
         assert relerr(phi, base) < tol_t, prec
 
 
+def test_charges_on_one_vertical_line(dev, F, oracle_mod):
+    """Every pair at rho = 0 (all points at x = y = 0, random heights in three
+    layers): the rho = 0 paths of the Sommerfeld integrals (orders m > 0 vanish),
+    M2L offsets on the axis and a deep tree.  FP64 form p = 12, default MAC,
+    against the image-series direct sum."""
+    import torch
+    rng = np.random.default_rng(81)
+    n = 1500
+    lay = np.repeat([0, 1, 2], n // 3).astype(np.int32)
+    zr = {0: (0.1, 1.1), 1: (-0.9, -0.1), 2: (-2.0, -1.1)}
+    z = np.array([rng.uniform(*zr[int(v)]) for v in lay])
+    x = np.zeros(n)
+    q = rng.uniform(-1, 1, n)
+    ref = oracle_mod.potential(D3, E3, x, x, z, lay, q, method="image3")
+    pl = F.Plan(D3, E3, x, x, z, lay, p=12, leaf_cap=20)
+    phi = pl.eval(torch.tensor(q, device=dev)).cpu().numpy()
+    st = pl.stats()
+    pl.close()
+    e = relerr(phi, ref)
+    _say(f"  vertical line: {e:.2e}, {st['max_level']} levels")
+    assert st["max_level"] >= 6
+    assert e < 1e-9
+
+
 def test_high_contrast_medium(dev, F, oracle_mod):
     """eps = (1, 80, 1): reflections of magnitude 0.975 give the density sharp
     resonances along the imaginary axis.  The contour form's integrals stay within
