@@ -91,6 +91,32 @@ def test_fp32_four_million_points(dev, F, oracle_mod):
     assert e <= 1e-5
 
 
+def test_single_interface_fp32_and_batched(dev, F, oracle_mod):
+    """One interface (two half-spaces, eps 2 and 9): the FP32 form and the batched
+    FP32 form (three vectors, batched kernels forced) against the quadrature direct
+    sum, <= 1e-5; the batched result is linear in the charges."""
+    import torch
+    rng = np.random.default_rng(91)
+    d, eps = [0.0], [2.0, 9.0]
+    n = 3000
+    lay = np.repeat([0, 1], n // 2).astype(np.int32)
+    z = np.where(lay == 0, rng.uniform(0.05, 1.0, n), rng.uniform(-1.0, -0.05, n))
+    x, y, q = rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), rng.uniform(-1, 1, n)
+    ref = oracle_mod.potential(d, eps, x, y, z, lay, q, method="quad")
+    qt = torch.tensor(q, device=dev)
+    pl = F.Plan(d, eps, x, y, z, lay, p=10, leaf_cap=32, precision=1, mac_d2=4)
+    e = relerr(pl.eval(qt).cpu().numpy(), ref)
+    pl.close()
+    pl = F.Plan(d, eps, x, y, z, lay, p=10, leaf_cap=32, precision=1, mac_d2=4, max_rhs=8)
+    pl.set_variants(batch_min=2)
+    phi = pl.eval(torch.stack([qt, -qt, 2 * qt])).cpu().numpy()
+    pl.close()
+    eb = relerr(phi[0], ref)
+    _say(f"  one interface: fp32 {e:.2e} batched {eb:.2e}")
+    assert e <= 1e-5 and eb <= 1e-5
+    assert relerr(phi[2], 2 * phi[0]) < 1e-6 and relerr(-phi[1], phi[0]) < 1e-6
+
+
 def test_fp32_six_region_medium(dev, F, oracle_mod):
     """The six-region medium (five interfaces, about 100 reaction components, the
     FP32 form's sparse top levels and reaction chunks all in play) against the
