@@ -35,7 +35,7 @@ STAGE_KERNEL = {"m2l": "m2l_mfma32_kernel", "p2p_free": "p2p_leaf_kernel<float>"
 CALIB_BYTES = 256 << 20  # plain device-to-device copy that scales the PMC byte counters
 PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32, vector and dense matrix (published), FLOP/s
-# Plain VALU issue rate with packed FP32 off (as this build compiles): 256 CUs x 4 SIMDs x 16
+# Plain VALU issue rate with packed FP32 off (as the library is compiled): 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 8 VALU
 # instructions per pair (3 sub, mul and 2 fma for r^2, rsq, fma into the sum; the
 # zero-distance compare and select run only over a leaf's own points) for the 11 flops
