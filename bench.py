@@ -186,10 +186,12 @@ def main():
     ap.add_argument("--leaf-cap-fp64", type=int, default=192)
     ap.add_argument("--mac", type=int, default=4)
     ap.add_argument("--rhs", type=int, default=1, help="charge vectors per evaluation (batched form)")
-    ap.add_argument("--cpu-sample", type=int, default=4096,
-                    help="oracle targets of the error subsample")
-    ap.add_argument("--cpu-timed", type=int, default=1536,
-                    help="first targets of the subsample timed as the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="oracle targets of the error subsample (default 4096; 16 where the oracle "
+                         "needs quadrature, media other than three layers)")
+    ap.add_argument("--cpu-timed", type=int, default=None,
+                    help="first targets of the subsample timed as the CPU baseline (default 1536; 8 "
+                         "with quadrature)")
     ap.add_argument("--solve-n", type=int, default=1048576,
                     help="panels of the capacitance-style GMRES solve (0: skip it)")
     args = ap.parse_args()
@@ -234,10 +236,16 @@ def main():
     # CPU baseline: the oracle timed on a bounded slice of the error subsample (about 10-30 s
     # on the host's cores); the rest of the subsample completes the error reference
     import oracle
-    rng = np.random.default_rng(0)
-    tgt = np.sort(rng.choice(n, args.cpu_sample, replace=False))
-    timed = tgt[: min(len(tgt), args.cpu_timed)]
+    # the three-layer oracle sums image series; other media need its quadrature,
+    # about a thousand times slower a pair, so their samples are smaller
     method = "image3" if len(w["d"]) == 2 else "quad"
+    n_sample = args.cpu_sample or (4096 if method == "image3" else 16)
+    n_timed = args.cpu_timed or (1536 if method == "image3" else 8)
+    rng = np.random.default_rng(0)
+    tgt = np.sort(rng.choice(n, min(n_sample, n), replace=False))
+    timed = tgt[: min(len(tgt), n_timed)]
+    print(f"[bench] cpu baseline: oracle ({method}) on {len(timed)} timed + {len(tgt) - len(timed)} more "
+          f"targets", file=sys.stderr, flush=True)
     c0 = time.perf_counter()
     ref_a = oracle.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
                              targets=timed, method=method)
