@@ -96,3 +96,19 @@ def test_workload_geometry():
     # self term of a square panel of side 2a: 8 a ln(1 + sqrt 2) / (4 pi (2a)^2)
     a = 0.01
     assert abs(W._rect_self_integral(a, a) - 8 * a * np.log(1 + np.sqrt(2))) <= 1e-15
+
+
+def test_rectangular_panel_self_integral():
+    """The closed form of int over [-a, a] x [-b, b] of dA / r for rectangles, against
+    adaptive quadrature in polar coordinates about the centre (the integrand's
+    singularity cancels against the Jacobian: int dtheta int_0^{R(theta)} dr)."""
+    from scipy.integrate import quad
+    for a, b in [(0.5, 0.5), (1.0, 0.25), (0.03, 0.7), (2.0, 1.0)]:
+        # r runs from 0 to the rectangle's edge along each direction
+        def edge(t):
+            c, s = abs(np.cos(t)), abs(np.sin(t))
+            return min(a / c if c > 0 else np.inf, b / s if s > 0 else np.inf)
+        corner = np.arctan2(b, a)
+        val = 4 * (quad(edge, 0, corner, epsabs=0, epsrel=1e-13)[0]
+                   + quad(edge, corner, np.pi / 2, epsabs=0, epsrel=1e-13)[0])
+        assert abs(W._rect_self_integral(a, b) - val) <= 1e-11 * val, (a, b)
