@@ -92,3 +92,55 @@ def test_adam_first_step_has_size_lr():
     g = rng.normal(size=50)
     t1, m, v = mlp.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3, eps=0.0)
     np.testing.assert_allclose(th - t1, 1e-3 * np.sign(g), rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_lr_every_step():
+    """With the same gradient g at every step, the bias-corrected moments are exactly
+    m_t / (1 - beta1^t) = g and v_t / (1 - beta2^t) = g^2 for every t (both geometric
+    sums telescope), so each step moves every parameter by lr * sign(g) (eps = 0).
+    Without the correction, or with t frozen at 1, step 2 would move 4.25 lr or 1.34 lr."""
+    rng = np.random.default_rng(11)
+    th = rng.normal(size=40)
+    g = rng.normal(size=40)
+    m = np.zeros(40)
+    v = np.zeros(40)
+    cur = th.copy()
+    for t in range(1, 6):
+        nxt, m, v = mlp.adam_step(cur, g, m, v, t, 1e-3, eps=0.0)
+        np.testing.assert_allclose(cur - nxt, 1e-3 * np.sign(g), rtol=1e-10)
+        cur = nxt
+
+
+def test_adam_alternating_gradient_second_step():
+    """Gradients g then -g (worked by hand): m_2 = 0.9 (0.1 g) - 0.1 g = -0.01 g,
+    v_2 = 0.999 (0.001 g^2) + 0.001 g^2 = 0.001999 g^2; the corrections divide by
+    1 - 0.81 = 0.19 and 1 - 0.998001 = 0.001999, so the second step is
+    -lr (-0.01 / 0.19) sign(g) = +lr sign(g) / 19."""
+    g = np.array([2.0, -0.5, 1e-3])
+    th = np.array([0.3, -0.2, 0.1])
+    lr = 1e-2
+    t1, m, v = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, lr, eps=0.0)
+    t2, m, v = mlp.adam_step(t1, -g, m, v, 2, lr, eps=0.0)
+    np.testing.assert_allclose(m, -0.01 * g, rtol=1e-12)
+    np.testing.assert_allclose(v, 0.001999 * g * g, rtol=1e-12)
+    np.testing.assert_allclose(t2 - t1, lr * np.sign(g) / 19.0, rtol=1e-10)
+
+
+def test_adam_third_step_after_one_kick():
+    """Gradients g, 0, 0 (worked by hand): m_3 = 0.81 (0.1 g) = 0.081 g,
+    v_3 = 0.998001 (0.001 g^2); corrected: 0.081 / 0.271 g and
+    0.000998001 / 0.002997001 g^2, so step 3 is lr * 0.2988929889 / 0.5770614256 sign(g)."""
+    g = np.array([3.0, -0.25])
+    th = np.array([1.0, 1.0])
+    lr = 1e-3
+    m = np.zeros(2)
+    v = np.zeros(2)
+    cur = th
+    for t, gt in ((1, g), (2, 0 * g), (3, 0 * g)):
+        nxt, m, v = mlp.adam_step(cur, gt, m, v, t, lr, eps=0.0)
+        if t < 3:
+            cur = nxt
+    mh = 0.081 / 0.271
+    vh = 0.000998001 / 0.002997001
+    np.testing.assert_allclose(cur - nxt, lr * mh / np.sqrt(vh) * np.sign(g), rtol=1e-9)
+    np.testing.assert_allclose(mh / np.sqrt(vh), 0.2988929889 / 0.5770614256, rtol=1e-9)

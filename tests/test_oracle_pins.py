@@ -317,6 +317,17 @@ def test_sommerfeld_image3_vs_high_precision(oracle_mod):
         assert im == pytest.approx(mp, rel=1e-11, abs=1e-14)
 
 
+def test_sommerfeld_contour_path_vs_closed_forms(oracle_mod):
+    """The K_m contour form of eq. contourchange (rho > z), integrated at 16 digits,
+    against closed forms that use no quadrature: sigma == 1 (Legendre closed form of the
+    Sommerfeld identity) and a three-layer component through its image series."""
+    v = oracle_mod.sommerfeld_mp([], [], 0, 0, 1, 1, 2, 1, 0.7, 0.2, 0.5, dps=16, path="contour")
+    assert v == pytest.approx(oracle_mod.sommerfeld_sigma1(2, 1, 0.7, 0.2, 0.5), rel=1e-13)
+    v = oracle_mod.sommerfeld_mp(D3, E3, 0, 2, 1, 2, 2, 1, 1.3, 0.4, 0.5, dps=16, path="contour")
+    want = oracle_mod.sommerfeld_image3(D3, E3, 0, 2, 1, 2, 2, 1, 1.3, 0.4, 0.5)
+    assert v == pytest.approx(want, rel=1e-13)
+
+
 def test_paper_recurrence_holds_on_closed_forms(oracle_mod):
     """eq. recurrence: S^n I_{n,m+1} = 2m/a_{n+m} (S/rho) S^{n-1} I_{n-1,m}
     - a_{n-m}/a_{n+m} S^n I_{n,m-1}, a_n = sqrt(n(n+1)), on closed-form values."""
