@@ -45,6 +45,8 @@ extern "C" {
 #define FMMLM_EDEVICE (-6)       /* a HIP call failed */
 #define FMMLM_ENOMEM (-7)        /* host or device allocation failed, or a list exceeds its limit */
 #define FMMLM_EUNSUPPORTED (-8)  /* option combination not built */
+#define FMMLM_EBUSY (-9)         /* the plan is in use: another call is enqueuing work on it, or its
+                                    last evaluation, enqueued on another stream, has not finished */
 
 /* ---- options --------------------------------------------------------------- */
 #define FMMLM_PMAX 16            /* largest truncation order p (n = 0..p) */
@@ -132,7 +134,14 @@ int fmm_layered_plan(int32_t n_interfaces, const double* z_interfaces, const dou
  *  hip_stream     all work is enqueued here; nothing is synchronised
  *
  * The plan owns one workspace: evaluations of one plan must not overlap in
- * time (enqueue them on one stream).  Errors: FMMLM_EINVAL, FMMLM_EDEVICE.
+ * time (enqueue them on one stream).  An evaluation is refused with
+ * FMMLM_EBUSY while another host thread is inside fmm_layered_eval or
+ * fmm_layered_solve on the plan, or when the plan's last evaluation was
+ * enqueued on another stream and has not finished (the check uses an event
+ * recorded after each evaluation; it is skipped while hip_stream is being
+ * captured into a graph).  Errors: FMMLM_EINVAL (null plan, q or phi; nrhs
+ * outside 1..max_rhs; ldq or ldphi below n; parts empty or with unknown bits),
+ * FMMLM_EBUSY, FMMLM_EDEVICE.
  */
 int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t ldq,
                      double* phi, int64_t ldphi, uint32_t parts, void* hip_stream);
@@ -197,8 +206,8 @@ int fmm_layered_plan_general(int32_t n_interfaces, const double* z_interfaces, c
  * Workspace: (restart + 1) n doubles plus small buffers, allocated and freed
  * by the call.  Evaluations of the plan must not overlap the call.
  * Errors: FMMLM_EINVAL (null plan, b, x or info; restart outside 1..256;
- * max_iters < 1; tol not in (0, 1); x overlapping b), FMMLM_ENOMEM,
- * FMMLM_EDEVICE.  With the plan's graph option every step captures anew (the
+ * max_iters < 1; tol not in (0, 1); x overlapping b), FMMLM_EBUSY (as for
+ * fmm_layered_eval), FMMLM_ENOMEM, FMMLM_EDEVICE.  With the plan's graph option every step captures anew (the
  * vectors change from step to step): leave it off for solves.
  */
 typedef struct {
@@ -422,6 +431,24 @@ int fmm_layered_surrogate_params(fmmlm_surrogate_t s, float* get, const float* s
  * For checking the training kernels. */
 int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
                                const float* target, double* loss, float* grad, void* hip_stream);
+
+/* The network's outputs (the remainder of the initial values in output units,
+ * before the closed-form parts are added) for n samples: host arrays comp [n],
+ * feat [n][4] as for fmm_layered_surrogate_grad, out [n][nout].  The same forward
+ * kernel as the plans' learned form.  Errors: FMMLM_EINVAL, FMMLM_ENOMEM,
+ * FMMLM_EDEVICE. */
+int fmm_layered_surrogate_forward(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
+                                  float* out, void* hip_stream);
+
+/* nsteps (1..64) steps of the training's Adam update (Kingma & Ba 2015, Algorithm 1:
+ * beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments) applied in place to the
+ * network's parameters, starting from zero moments at t = 1: step t uses the
+ * gradient grads [t-1][nparams] and the learning rate lr [t-1] (host arrays).
+ * The parameters after each step go to params_out [nsteps][nparams] (host, may be
+ * NULL).  For checking the training kernel.  Errors: FMMLM_EINVAL (lr not finite
+ * and positive), FMMLM_ENOMEM, FMMLM_EDEVICE. */
+int fmm_layered_surrogate_adam(fmmlm_surrogate_t s, int32_t nsteps, const float* grads, const double* lr,
+                               float* params_out, void* hip_stream);
 
 /* The training samples fmm_layered_surrogate_train draws for seed: n samples
  * into host arrays comp [n], rho [n], zeta [n], feat [n][4], target [n][nout]

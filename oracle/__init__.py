@@ -101,6 +101,8 @@ def _load():
         lib.oracle_potential_ab.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -115,6 +117,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (OpenMP)."""
+    _load().oracle_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

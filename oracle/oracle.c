@@ -44,6 +44,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of later parallel loops (a single-core timing of the oracle uses 1). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static int valid_side(int L, int layer, int side) {
   return side == 1 ? (layer <= L - 1) : (layer >= 1);
 }

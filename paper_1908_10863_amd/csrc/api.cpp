@@ -309,7 +309,7 @@ void drop_graph(fmmlm_plan_s* P) {
 void free_plan(fmmlm_plan_s* P) {
   if (!P) return;
   drop_graph(P);
-  for (hipEvent_t e : {P->ev_q, P->ev_m, P->ev_near, P->ev_top, P->ev_l})
+  for (hipEvent_t e : {P->ev_q, P->ev_m, P->ev_near, P->ev_top, P->ev_l, P->ev_done})
     if (e) (void)hipEventDestroy(e);
   for (hipStream_t q : {P->s_near, P->s_top})
     if (q) (void)hipStreamDestroy(q);
@@ -1213,7 +1213,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if ((rc = dev_alloc(P, &P->phin, P->NP))) return rc;
   FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_near, hipStreamNonBlocking));
   FMM_HIP_TRY(hipStreamCreateWithFlags(&P->s_top, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&P->ev_q, &P->ev_m, &P->ev_near, &P->ev_top, &P->ev_l})
+  for (hipEvent_t* e : {&P->ev_q, &P->ev_m, &P->ev_near, &P->ev_top, &P->ev_l, &P->ev_done})
     FMM_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if ((rc = dev_alloc(P, &P->M, (size_t)P->NB * nrr * G))) return rc;
   if ((rc = dev_alloc(P, &P->Lx, (size_t)P->NB * nrr * G))) return rc;
@@ -1570,6 +1570,49 @@ int fmm_layered_plan_general(int32_t n_interfaces, const double* z_interfaces, c
                    out);
 }
 
+}  // extern "C"
+
+namespace fmmlm {
+
+int plan_acquire(fmmlm_plan_s* P, hipStream_t st) {
+  if (P->busy.exchange(1)) {
+    set_last_error("another call is enqueuing work on the plan");
+    return FMMLM_EBUSY;
+  }
+  if (P->done_recorded && st != P->done_stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    if (!capturing) {
+      const hipError_t e = hipEventQuery(P->ev_done);
+      (void)hipGetLastError();  // a pending event is not an error of the next call
+      if (e == hipErrorNotReady) {
+        P->busy.store(0);
+        set_last_error("the plan's last evaluation, on another stream, has not finished");
+        return FMMLM_EBUSY;
+      }
+    }
+    (void)hipGetLastError();
+  }
+  return FMMLM_OK;
+}
+
+void plan_release(fmmlm_plan_s* P, hipStream_t st, bool record) {
+  if (record && P->ev_done) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    (void)hipGetLastError();
+    if (!capturing && hipEventRecord(P->ev_done, st) == hipSuccess) {
+      P->done_stream = st;
+      P->done_recorded = true;
+    }
+  }
+  P->busy.store(0);
+}
+
+}  // namespace fmmlm
+
+extern "C" {
+
 int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t ldq, double* phi, int64_t ldphi,
                      uint32_t parts, void* hip_stream) {
   if (!plan || !q || !phi) return FMMLM_EINVAL;
@@ -1577,6 +1620,19 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   if (ldq < plan->N || ldphi < plan->N) return FMMLM_EINVAL;
   if (parts == 0 || (parts & ~(FMMLM_FREE | FMMLM_REACTION))) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int rc = plan_acquire(plan, st);
+  if (rc) return rc;
+  rc = fmmlm::eval_held(plan, nrhs, q, ldq, phi, ldphi, parts, st);
+  plan_release(plan, st, rc == FMMLM_OK);
+  return rc;
+}
+
+}  // extern "C"
+
+// The evaluation proper, for a caller that holds the plan (plan_acquire) and
+// has checked the arguments.
+int fmmlm::eval_held(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t ldq, double* phi, int64_t ldphi,
+                     uint32_t parts, hipStream_t st) {
   auto launch = [&]() -> int {
     if (nrhs < plan->batch_min) {
       for (int r = 0; r < nrhs; ++r) {
@@ -1638,6 +1694,8 @@ int fmm_layered_eval(fmmlm_plan_t plan, int32_t nrhs, const double* q, int64_t l
   return rc;
 }
 
+extern "C" {
+
 int fmm_layered_plan_set_variants(fmmlm_plan_t plan, int32_t m2l_variant, int32_t batch_variant,
                                   int32_t batch_min_rhs) {
   if (!plan) return FMMLM_EINVAL;
@@ -1672,10 +1730,11 @@ const char* fmm_layered_strerror(int code) {
     case FMMLM_EDEVICE: base = "HIP error"; break;
     case FMMLM_ENOMEM: base = "out of memory or list limit exceeded"; break;
     case FMMLM_EUNSUPPORTED: base = "unsupported option combination"; break;
+    case FMMLM_EBUSY: base = "the plan is in use by another evaluation"; break;
     default: break;
   }
   msg = base;
-  if (code == FMMLM_EDEVICE || code == FMMLM_ENOMEM) {
+  if (code == FMMLM_EDEVICE || code == FMMLM_ENOMEM || code == FMMLM_EBUSY) {
     if (!g_last_error.empty()) msg += ": " + g_last_error;
   }
   return msg.c_str();
@@ -2004,6 +2063,76 @@ int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* co
   hipFree(df);
   hipFree(dy);
   hipFree(dg);
+  return rc;
+}
+
+int fmm_layered_surrogate_forward(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
+                                  float* out, void* hip_stream) {
+  if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !feat || !out) return FMMLM_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (comp[i] < 0 || comp[i] >= s->net.ncomp) return FMMLM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nout = s->net.nout;
+  int32_t* dc = nullptr;
+  float *df = nullptr, *dy = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, n * sizeof(int32_t)));
+  if (hipMalloc(&df, n * 4 * sizeof(float)) != hipSuccess || hipMalloc(&dy, (size_t)n * nout * sizeof(float)) != hipSuccess) {
+    hipFree(dc);
+    hipFree(df);
+    set_last_error("fmm_layered_surrogate_forward: allocation failed");
+    return FMMLM_ENOMEM;
+  }
+  int rc = FMMLM_OK;
+  hipError_t e = hipMemcpy(dc, comp, n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(df, feat, n * 4 * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  if (rc == FMMLM_OK) rc = gpu_mlp_forward(s->net, dc, df, n, dy, nout, nout, nullptr, nullptr, nullptr, st);
+  if (rc == FMMLM_OK) {
+    e = hipMemcpy(out, dy, (size_t)n * nout * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(dc);
+  hipFree(df);
+  hipFree(dy);
+  return rc;
+}
+
+int fmm_layered_surrogate_adam(fmmlm_surrogate_t s, int32_t nsteps, const float* grads, const double* lr,
+                               float* params_out, void* hip_stream) {
+  if (!s || nsteps < 1 || nsteps > 64 || !grads || !lr) return FMMLM_EINVAL;
+  for (int t = 0; t < nsteps; ++t)
+    if (!std::isfinite(lr[t]) || !(lr[t] > 0.0)) return FMMLM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t bytes = (size_t)nsteps * s->net.nparams * sizeof(float);
+  float *dg = nullptr, *dt = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dg, bytes));
+  if (hipMalloc(&dt, bytes) != hipSuccess) {
+    hipFree(dg);
+    set_last_error("fmm_layered_surrogate_adam: allocation failed");
+    return FMMLM_ENOMEM;
+  }
+  int rc = FMMLM_OK;
+  hipError_t e = hipMemcpy(dg, grads, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  if (rc == FMMLM_OK) rc = gpu_mlp_adam_steps(s->net, nsteps, dg, lr, dt, st);
+  if (rc == FMMLM_OK && params_out) {
+    e = hipMemcpy(params_out, dt, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(dg);
+  hipFree(dt);
   return rc;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <array>
@@ -241,6 +242,12 @@ struct fmmlm_plan_s {
   // live stage timing
   std::vector<hipEvent_t> prof_ev;  // [max_evals][FMMLM_NSTAGES + 1]
   int prof_cap = 0, prof_used = 0;
+  // overlap detection (FMMLM_EBUSY): set while a call enqueues work on the plan;
+  // the last evaluation's end, recorded on its stream
+  std::atomic<int> busy{0};
+  hipEvent_t ev_done = nullptr;
+  hipStream_t done_stream = nullptr;
+  bool done_recorded = false;
 };
 
 namespace fmmlm {
@@ -305,6 +312,8 @@ int gpu_mlp_train(const MlpNet& net, const int32_t* comp, const float* feat, con
                   hipStream_t st);
 int gpu_mlp_grad(const MlpNet& net, const int32_t* comp, const float* feat, const float* y, int64_t n,
                  float* grad, double* loss, hipStream_t st);
+int gpu_mlp_adam_steps(const MlpNet& net, int nsteps, const float* grads, const double* lr, float* trace,
+                       hipStream_t st);
 // d_lad: ladder coefficients [surrogate component][kLadder] (device)
 int gpu_surrogate_samples(const Medium& md, const std::vector<CompInfo>& comps, const double* d_lad,
                           const SurrogateDomain& dm, int nmax, uint64_t seed, int64_t n, int32_t* d_comp,
@@ -337,6 +346,15 @@ int gpu_eval_one(fmmlm_plan_s* P, const double* q, double* phi, uint32_t parts, 
                  hipEvent_t* ev);
 
 void set_last_error(const std::string& s);
+
+// Takes the plan for one call (eval, solve): FMMLM_EBUSY when another call is
+// enqueuing work on it, or when its last evaluation, enqueued on a stream
+// other than st, has not finished.  plan_release gives it back and, with
+// record, marks the end of the work just enqueued on st.
+int plan_acquire(fmmlm_plan_s* P, hipStream_t st);
+void plan_release(fmmlm_plan_s* P, hipStream_t st, bool record);
+int eval_held(fmmlm_plan_s* P, int32_t nrhs, const double* q, int64_t ldq, double* phi, int64_t ldphi,
+              uint32_t parts, hipStream_t st);
 
 // sides (layer, side) of a medium in the surrogate's numbering
 inline int side_index(int L, int layer, int side) {

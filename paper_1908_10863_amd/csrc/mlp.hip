@@ -440,6 +440,34 @@ int gpu_mlp_grad(const MlpNet& net, const int32_t* comp, const float* feat, cons
   return FMMLM_OK;
 }
 
+// nsteps Adam steps t = 1..nsteps from zero moments with the given gradients
+// (device, [nsteps][nparams]) and learning rates (host), through the training
+// kernel; the parameters after each step go to trace (device, [nsteps][nparams])
+// when it is not null.
+int gpu_mlp_adam_steps(const MlpNet& net, int nsteps, const float* grads, const double* lr, float* trace,
+                       hipStream_t st) {
+  if (nsteps < 1) return FMMLM_EINVAL;
+  Work wk;
+  float *m, *v;
+  int rc;
+  if ((rc = wk.get(&m, net.nparams)) || (rc = wk.get(&v, net.nparams))) return rc;
+  FMM_HIP_TRY(hipMemsetAsync(m, 0, net.nparams * sizeof(float), st));
+  FMM_HIP_TRY(hipMemsetAsync(v, 0, net.nparams * sizeof(float), st));
+  const double beta1 = 0.9, beta2 = 0.999;
+  for (int t = 1; t <= nsteps; ++t) {
+    adam_kernel<<<256, 256, 0, st>>>(net.params, grads + (int64_t)(t - 1) * net.nparams, m, v, net.nparams,
+                                     (float)lr[t - 1], (float)beta1, (float)beta2,
+                                     (float)(1.0 / (1.0 - std::pow(beta1, t))),
+                                     (float)(1.0 / (1.0 - std::pow(beta2, t))), 1e-8f);
+    FMM_HIP_TRY(hipGetLastError());
+    if (trace)
+      FMM_HIP_TRY(hipMemcpyAsync(trace + (int64_t)(t - 1) * net.nparams, net.params, net.nparams * sizeof(float),
+                                 hipMemcpyDeviceToDevice, st));
+  }
+  FMM_HIP_TRY(hipStreamSynchronize(st));
+  return FMMLM_OK;
+}
+
 // Adam over `steps` minibatches of B samples drawn from the n training samples.
 // Learning rate: linear warm-up over the first 2% of the steps, then cosine
 // decay from lr to lr/100.  Mean minibatch loss of the first and last 2% of

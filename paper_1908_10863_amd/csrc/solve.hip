@@ -128,6 +128,13 @@ extern "C" int fmm_layered_solve(fmmlm_plan_t plan, const double* diag, const do
   const int64_t n = plan->N;
   if (x < b + n && b < x + n) return FMMLM_EINVAL;  // x must not overlap b
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (int rc = plan_acquire(plan, st)) return rc;
+  // every step synchronises st, so the plan is free again when the call returns
+  struct Hold {
+    fmmlm_plan_s* P;
+    hipStream_t st;
+    ~Hold() { plan_release(P, st, false); }
+  } hold{plan, st};
   *info = fmmlm_solve_info{0, 0, 0, 0, 0.0, 0.0, 0.0};
   const int m = o.restart;
   const int64_t ldv = n;
@@ -156,7 +163,7 @@ extern "C" int fmm_layered_solve(fmmlm_plan_t plan, const double* diag, const do
   };
   // G v + diag v into w
   auto matvec = [&](const double* v, double* w) -> int {
-    if (int rc = fmm_layered_eval(plan, 1, v, n, w, n, FMMLM_FREE | FMMLM_REACTION, hip_stream)) return rc;
+    if (int rc = eval_held(plan, 1, v, n, w, n, FMMLM_FREE | FMMLM_REACTION, st)) return rc;
     if (diag) gm_diag_kernel<<<nb, kSolveThreads, 0, st>>>(n, diag, v, w);
     info->matvecs++;
     return FMMLM_OK;

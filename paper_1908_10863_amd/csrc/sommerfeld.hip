@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "fmm_internal.h"
@@ -635,15 +636,23 @@ void gl_nodes(int n, double* x, double* w) {
   }
 }
 
+// The node table lives in constant memory, one copy per device: it is
+// written once on each device the library runs on.
+constexpr int kMaxDevices = 64;
 int upload_gl(hipStream_t st) {
-  static bool done = false;
+  static std::mutex mu;
+  static bool done[kMaxDevices] = {};
   (void)st;
-  if (done) return FMMLM_OK;
+  int dev = 0;
+  FMM_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FMMLM_EDEVICE;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done[dev]) return FMMLM_OK;
   double x[kGL], w[kGL];
   gl_nodes(kGL, x, w);
   FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(x)));
   FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(w)));
-  done = true;
+  done[dev] = true;
   return FMMLM_OK;
 }
 

@@ -21,7 +21,7 @@ REACTION = 2
 
 _ERRORS = {
     -1: ValueError, -2: ValueError, -3: ValueError, -4: ValueError, -5: ValueError,
-    -6: RuntimeError, -7: MemoryError, -8: NotImplementedError,
+    -6: RuntimeError, -7: MemoryError, -8: NotImplementedError, -9: RuntimeError,
 }
 
 
@@ -88,7 +88,8 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
            "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve",
-           "fmm_layered_plan_general"]
+           "fmm_layered_plan_general",
+           "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -164,6 +165,10 @@ def lib():
     L.fmm_layered_surrogate_eval.restype = ctypes.c_int
     L.fmm_layered_surrogate_samples.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp]
     L.fmm_layered_surrogate_samples.restype = ctypes.c_int
+    L.fmm_layered_surrogate_forward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.fmm_layered_surrogate_forward.restype = ctypes.c_int
+    L.fmm_layered_surrogate_adam.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
+    L.fmm_layered_surrogate_adam.restype = ctypes.c_int
     L.fmm_layered_plan_set_variants.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.fmm_layered_plan_set_variants.restype = ctypes.c_int
     L.fmm_layered_profile_begin.argtypes = [vp, ctypes.c_int32]
@@ -406,6 +411,26 @@ class Surrogate:
         check(lib().fmm_layered_surrogate_grad(self._h, n, _ptr(comp), _ptr(feat), _ptr(target),
                                                ctypes.byref(loss), _ptr(g), _stream_handle(stream)))
         return loss.value, g
+
+    def forward(self, comp, feat, stream=None):
+        """Network outputs [n, nout] (FP32) for components comp [n] and features feat [n, 4]."""
+        comp = _host(comp, np.int32)
+        feat = _host(feat, np.float32)
+        out = np.zeros((len(comp), self.nout), np.float32)
+        check(lib().fmm_layered_surrogate_forward(self._h, len(comp), _ptr(comp), _ptr(feat), _ptr(out),
+                                                  _stream_handle(stream)))
+        return out
+
+    def adam(self, grads, lr, stream=None):
+        """Adam steps t = 1..len(grads) from zero moments with the given gradients [nsteps, nparams]
+        and learning rates [nsteps]; updates the parameters in place and returns them after each
+        step [nsteps, nparams]."""
+        grads = _host(np.atleast_2d(grads), np.float32)
+        lr = _host(np.broadcast_to(np.asarray(lr, np.float64), (grads.shape[0],)), np.float64)
+        out = np.zeros_like(grads)
+        check(lib().fmm_layered_surrogate_adam(self._h, grads.shape[0], _ptr(grads), _ptr(lr), _ptr(out),
+                                               _stream_handle(stream)))
+        return out
 
     def samples(self, n, seed=1, stream=None):
         """The training samples for seed: (comp, rho, zeta, feat [n, 4], target [n, nout])."""

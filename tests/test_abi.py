@@ -66,7 +66,8 @@ def _plan_rc(L, d, eps, x, y, z, lay, p, opts=None):
 
 @pytest.mark.parametrize("case,code", [
     ("p0", -1), ("p17", -1), ("interfaces_up", -2), ("eps_neg", -3), ("eps_nan", -3),
-    ("layer_range", -4), ("outside_layer", -4), ("nan_coord", -1),
+    ("layer_range", -4), ("outside_layer", -4), ("nan_coord", -1), ("on_interface", -5),
+    ("on_lower_interface", -5), ("near_interface", -5),
 ])
 def test_plan_validation_errors(L, case, code):
     d, eps = [0.0, -1.0], [1.0, 5.0, 2.0]
@@ -87,6 +88,12 @@ def test_plan_validation_errors(L, case, code):
         z = [0.5, 0.5]
     elif case == "nan_coord":
         x = [float("nan"), 0.2]
+    elif case == "on_interface":
+        z = [0.0, -0.5]            # layer 0's bottom interface d_0 = 0
+    elif case == "on_lower_interface":
+        z = [0.5, -1.0]            # layer 1's bottom interface d_1 = -1
+    elif case == "near_interface":
+        z = [1e-14, -0.5]          # below 1e-12 of the root box side above d_0
     rc, h = _plan_rc(L, d, eps, x, y, z, lay, p)
     assert rc == code
     assert not h.value

@@ -81,6 +81,59 @@ def test_gradient_matches_oracle(dev, F):
         assert e <= 2e-5, name
 
 
+
+def test_forward_matches_oracle_elementwise(dev, F):
+    """The forward kernel (FP32, LDS-tiled) against the oracle's FP64 forward pass, output by
+    output, at parameters that drive every tanh layer into its nonlinear range."""
+    from oracle import mlp
+    _say("surrogate forward vs oracle")
+    s = F.Surrogate(D3, E3, p=4, rho_max=1.5, zeta_max=2.2, seed=5)
+    ncomp, nout = 16, 17
+    lay = mlp.layout(ncomp, nout)
+    rng = np.random.default_rng(6)
+    theta = (rng.normal(0.0, 1.0, lay["total"]) / np.sqrt(64.0)).astype(np.float32)
+    s.params(set_to=theta)
+    n = 333  # five full tiles of 64 and a ragged one
+    comp = rng.integers(0, ncomp, n).astype(np.int32)
+    feat = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    got = s.forward(comp, feat).astype(np.float64)
+    ref, (h1, h2, h3) = mlp.forward(theta.astype(np.float64), ncomp, nout, comp, feat.astype(np.float64))
+    assert np.mean(np.abs(h2) > 0.5) > 0.2  # the layers are not in their linear range
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    _say(f"  max |out - oracle| = {err:.2e} (max |out| {scale:.2f})")
+    # FP32: 128-term dot products and tanhf per layer, a few ulps of the output scale
+    np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6 * scale)
+
+
+def test_adam_kernel_matches_oracle_steps(dev, F):
+    """The training's Adam kernel, step by step from zero moments, against the oracle's
+    adam_step on the same gradients (varying learning rates, zero and tiny entries)."""
+    from oracle import mlp
+    _say("surrogate Adam kernel vs oracle")
+    s = F.Surrogate(D3, E3, p=4, rho_max=1.5, zeta_max=2.2, seed=7)
+    theta0 = s.params().astype(np.float64)
+    n = theta0.size
+    rng = np.random.default_rng(8)
+    steps = 5
+    grads = rng.normal(0.0, 1e-2, (steps, n)).astype(np.float32)
+    grads[:, :50] = 0.0                    # untouched parameters
+    grads[1, 50:100] = 0.0                 # a step without gradient after a kick
+    grads[:, 100:150] *= 1e-6              # tiny gradients (eps matters)
+    lr = np.array([1e-3, 2e-3, 5e-4, 1e-3, 3e-3])
+    trace = s.adam(grads, lr).astype(np.float64)
+    th = theta0.copy()
+    m = np.zeros(n)
+    v = np.zeros(n)
+    for t in range(steps):
+        th, m, v = mlp.adam_step(th, grads[t].astype(np.float64), m, v, t + 1, lr[t])
+        d = np.abs(trace[t] - th)
+        _say(f"  step {t + 1}: max |param - oracle| = {d.max():.2e}")
+        # FP32 moments and update (relative 1e-6 of a step of size <= lr), FP32 parameters
+        np.testing.assert_allclose(trace[t], th, rtol=4e-7, atol=1e-6 * lr.sum())
+    np.testing.assert_array_equal(trace[-1][:50], theta0[:50].astype(np.float32))
+    np.testing.assert_array_equal(s.params(), trace[-1].astype(np.float32))
+
 def test_params_roundtrip_and_validation(dev, F):
     s = F.Surrogate(D3, E3, p=3, rho_max=1.0, zeta_max=1.0, seed=5)
     th = s.params()
