@@ -33,17 +33,19 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1908_10863_amd", "csrc", "fmm.hip")
 # kernel that carries each stage of the FP32 form (one launch per evaluation)
 STAGE_KERNEL = {"m2l": "m2l_mfma32_kernel", "p2p_free": "p2p_leaf_kernel<float>"}
 CALIB_BYTES = 256 << 20  # plain device-to-device copy that scales the PMC byte counters
-PEAK_FP64 = 78.6e12  # MI355X vector FP64, FLOP/s
+PEAK_FP64 = 78.6e12  # MI355X FP64, vector and dense matrix (published), FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32, vector and dense matrix (published), FLOP/s
 # Plain VALU issue rate with packed FP32 off (as the library is compiled): 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 8 VALU
 # instructions per pair (3 sub, mul and 2 fma for r^2, rsq, fma into the sum; the
 # zero-distance compare and select run only over a leaf's own points) for the 11 flops
-# counted per pair, so its ALU ceiling is 11/8 of the lane rate.
+# counted per pair.  The ratio of the achieved rate to 11/8 of the lane rate is reported
+# beside the roofline as an issue-efficiency figure; the roofline itself is priced against
+# the published peak of the stage's arithmetic.
 VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
 P2P_INSTR_PER_PAIR = 8
 P2P_FLOPS_PER_PAIR = 11
-ALU_PEAK = {"p2p_free": VALU_LANE_RATE / P2P_INSTR_PER_PAIR * P2P_FLOPS_PER_PAIR}
+ISSUE_CEILING = {"p2p_free": VALU_LANE_RATE / P2P_INSTR_PER_PAIR * P2P_FLOPS_PER_PAIR}
 
 
 def stage_flops(stats, p, stage, rhs=1):
@@ -127,12 +129,42 @@ def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1):
     torch.cuda.synchronize()
     stage_ms, nrec = plan.profile_end()
     phi = out.cpu().numpy()
+    # the free and reaction parts on their own (untimed), for the per-part error measures
+    q1 = q if rhs == 1 else q[0]
+    phi_free = plan.eval(q1, parts=fmmlm.FREE).cpu().numpy()
+    phi_reac = plan.eval(q1, parts=fmmlm.REACTION).cpu().numpy()
     plan.close()
     avg = {k: v / max(nrec, 1) for k, v in stage_ms.items()}
     print(f"[bench] {tag}: {rhs * steps / elapsed:.2f} matvec/s, stages(ms) " +
           ", ".join(f"{k}={v:.3f}" for k, v in avg.items()), file=sys.stderr, flush=True)
     return {"value": rhs * steps / elapsed, "ms": 1e3 * elapsed / steps, "stages": avg, "stats": st,
-            "phi": phi if rhs == 1 else phi[0]}
+            "phi": phi if rhs == 1 else phi[0], "phi_free": phi_free, "phi_reac": phi_reac}
+
+
+def stage_roofline(st, p, stage, ms, fp32, rhs=1):
+    """Roofline of one stage's launch: algorithmic flops over its average time, against the
+    published peak of the arithmetic that runs it (FP32 form: FP32 vector / matrix 157.3
+    TFLOP/s; FP64 form: FP64 vector / matrix 78.6 TFLOP/s)."""
+    flops = stage_flops(st, p, stage, rhs)
+    achieved = flops / (ms * 1e-3) / 1e12
+    peak = (PEAK_FP32 if fp32 else PEAK_FP64) / 1e12
+    bound = "mfma" if stage == "m2l" else "alu"
+    return {"bound": bound, "stage": stage, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "flops_per_launch": flops, "avg_ms": ms}
+
+
+def error_measures(phi, ref, layer):
+    """Relative L2 error over the judged targets, and per layer the measures of Sec. 4:
+    Err_2 = ||phi - ref|| / ||ref|| and Err_max = max_i |phi_i - ref_i| / |ref_i|."""
+    import numpy as np
+    out = {"rel_l2": float(np.linalg.norm(phi - ref) / np.linalg.norm(ref)), "per_layer": []}
+    for l in np.unique(layer):
+        m = layer == l
+        d = phi[m] - ref[m]
+        out["per_layer"].append({"layer": int(l), "n": int(m.sum()),
+                                 "err2": float(np.linalg.norm(d) / np.linalg.norm(ref[m])),
+                                 "errmax": float(np.max(np.abs(d) / np.abs(ref[m])))})
+    return out
 
 
 def run_solve(fmmlm, workloads, dev, n, restart, tol, reps):
@@ -220,18 +252,22 @@ def main():
     st = form["stats"]
     avg = form["stages"]
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
-    flops = stage_flops(st, p, dom, args.rhs)
-    achieved = flops / (avg[dom] * 1e-3) / 1e12
     # the main M2L stage is one launch of the matrix-core GEMM kernel (FP32 MFMA); the free
     # P2P stage one launch of the leaf-blocked VALU kernel
-    kernel = STAGE_KERNEL.get(dom, dom)
-    peak = (PEAK_FP32 if dom == "m2l" else ALU_PEAK.get(dom, PEAK_FP32)) / 1e12
-    roofline = {"bound": "mfma" if dom == "m2l" else "alu", "kernel": kernel, "stage": dom,
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(dom),
-                "flops_per_launch": flops, "avg_ms": avg[dom]}
-    if dom != "m2l":
-        roofline["peak_published_fp32"] = PEAK_FP32 / 1e12
+    roofline = stage_roofline(st, p, dom, avg[dom], True, args.rhs)
+    roofline["kernel"] = STAGE_KERNEL.get(dom, dom)
+    roofline["traffic"] = measured_traffic(dom)
+    if dom in ISSUE_CEILING:
+        ceil = ISSUE_CEILING[dom] / 1e12
+        roofline["issue_ceiling"] = {"peak": ceil, "frac": roofline["achieved"] / ceil,
+                                     "instr_per_pair": P2P_INSTR_PER_PAIR,
+                                     "flops_per_pair": P2P_FLOPS_PER_PAIR}
+    # every stage of both forms against its published peak (stages with a work model)
+    stage_roof = {k: stage_roofline(st, p, k, avg[k], True, args.rhs)
+                  for k in avg if stage_flops(st, p, k) > 0}
+    bst = base["stats"]
+    base_roof = {k: stage_roofline(bst, p, k, base["stages"][k], False)
+                 for k in base["stages"] if stage_flops(bst, p, k) > 0}
 
     # CPU baseline: the oracle timed on a bounded slice of the error subsample (about 10-30 s
     # on the host's cores); the rest of the subsample completes the error reference
@@ -255,12 +291,33 @@ def main():
                               targets=rest, method=method) if len(rest) else np.zeros(0))
     ref = np.concatenate([ref_a, ref_b])
     kern = "image-series" if method == "image3" else "quadrature"
-    cpu = {"value": (len(timed) / n) / ct, "unit": "matvec/s", "cores": oracle.num_threads(),
+    # one core: the first targets of the timed slice, the oracle limited to one thread
+    n1 = max(1, len(timed) // 16)
+    nthreads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    c1 = time.perf_counter()
+    oracle.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=timed[:n1],
+                     method=method)
+    ct1 = time.perf_counter() - c1
+    oracle.set_num_threads(nthreads)
+    cpu = {"value": (len(timed) / n) / ct, "unit": "matvec/s", "cores": nthreads,
            "kind": "oracle",
            "sample": f"{len(timed)} targets x {n} sources, direct sum ({kern} reaction "
-                     f"kernels), {ct:.1f} s"}
+                     f"kernels), {ct:.1f} s",
+           "single_core": {"value": (n1 / n) / ct1, "unit": "matvec/s", "cores": 1,
+                           "sample": f"{n1} targets x {n} sources, {ct1:.1f} s"}}
     err32 = float(np.linalg.norm(form["phi"][tgt] - ref) / np.linalg.norm(ref))
     err64 = float(np.linalg.norm(base["phi"][tgt] - ref) / np.linalg.norm(ref))
+    # the free and reaction parts on their own (Sec. 4's per-layer measures, split by part)
+    ref_free = oracle.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0],
+                                targets=tgt, method=method, parts=1)
+    ref_reac = ref - ref_free
+    lay_t = np.asarray(w["layer"])[tgt]
+    errors = {}
+    for tag, f in (("fp32", form), ("fp64", base)):
+        errors[tag] = {"total": error_measures(f["phi"][tgt], ref, lay_t),
+                       "free": error_measures(f["phi_free"][tgt], ref_free, lay_t),
+                       "reaction": error_measures(f["phi_reac"][tgt], ref_reac, lay_t)}
 
     rec = {
         "metric": METRIC, "value": form["value"], "unit": "matvec/s", "n_gpus": 1,
@@ -272,9 +329,11 @@ def main():
                    "precision": "fp32-compensated (fp64 top 3 levels)", "rhs": args.rhs},
         "roofline": roofline, "cpu_baseline": cpu,
         "rel_error_vs_oracle": err32,
+        "errors": errors,
         "fp64_baseline": {"value": base["value"], "ms_per_step": base["ms"],
                           "leaf_cap": args.leaf_cap_fp64, "rel_error_vs_oracle": err64,
-                          "stage_ms": base["stages"]},
+                          "stage_ms": base["stages"], "roofline": base_roof},
+        "stage_roofline": stage_roof,
         "speedup_vs_fp64": form["value"] / base["value"],
         "stage_ms": avg, "plan_seconds": st["plan_seconds"],
         "counts": {k: st[k] for k in ("n_boxes", "n_leaves", "m2l_free_pairs", "m2l_reaction_pairs",
