@@ -321,6 +321,23 @@ int fmm_layered_plan_tree(fmmlm_plan_t plan, int32_t t, int32_t* layer, int32_t*
                           int64_t* n, uint64_t* keys, int64_t* perm);
 
 /*
+ * The plan's interaction lists (Algorithm 1's interaction lists, checked by tests).
+ * Points are numbered in global tree order: the trees of fmm_layered_plan_tree
+ * concatenated in their order.  which selects the table; *count receives its
+ * rows; out (host, may be NULL to query the count) receives them:
+ *   0  boxes   [count][4]: first point, points, parent box (-1 for a root), level
+ *   1  M2L     [count][3]: target box, source box, 1 for a free-space entry (same
+ *              tree) or 0 for a reaction entry (the source tree's expansion,
+ *              mirrored, for the component of the target tree and source tree)
+ *   2  P2P free     [count][3]: target leaf box, first source point, source points
+ *   3  P2P reaction [count][3]: the same for the reaction near field
+ * A source's multipole expansion reaches a target through M2L between any
+ * ancestor-or-self of the source's leaf and any ancestor-or-self of the
+ * target's leaf.  Errors: FMMLM_EINVAL, FMMLM_EDEVICE.
+ */
+int fmm_layered_plan_lists(fmmlm_plan_t plan, int32_t which, int64_t* count, int32_t* out);
+
+/*
  * The scaled Sommerfeld-type integrals S^N I^{ab}_{N,M}(rho, z) of
  * eq. scaledsommerfeldint for 0 <= M <= N <= nmax, computed on the GPU the
  * way plans compute them: 4 nmax + 1 initial values (M = 0, 1), the rest by

@@ -1758,6 +1758,58 @@ int fmm_layered_plan_tree(fmmlm_plan_t plan, int32_t t, int32_t* layer, int32_t*
   return FMMLM_OK;
 }
 
+int fmm_layered_plan_lists(fmmlm_plan_t plan, int32_t which, int64_t* count, int32_t* out) {
+  if (!plan || !count || which < 0 || which > 3) return FMMLM_EINVAL;
+  auto get = [](const int32_t* d, int64_t n, std::vector<int32_t>& h) -> int {
+    h.assign((size_t)std::max<int64_t>(n, 0), 0);
+    if (n > 0) FMM_HIP_TRY(hipMemcpy(h.data(), d, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return FMMLM_OK;
+  };
+  int rc;
+  std::vector<int32_t> a, b, c, e;
+  if (which == 0) {
+    *count = plan->NB;
+    if (!out) return FMMLM_OK;
+    std::vector<int32_t> lev;
+    if ((rc = get(plan->bstart, plan->NB, a)) || (rc = get(plan->bcount, plan->NB, b)) ||
+        (rc = get(plan->bparent, plan->NB, c)) || (rc = get(plan->blevel, plan->NB, lev)))
+      return rc;
+    for (int64_t i = 0; i < plan->NB; ++i) {
+      out[4 * i] = a[i];
+      out[4 * i + 1] = b[i];
+      out[4 * i + 2] = c[i];
+      out[4 * i + 3] = lev[i];
+    }
+    return FMMLM_OK;
+  }
+  if (which == 1) {
+    if ((rc = get(plan->m2l_ptr, plan->NB + 1, a))) return rc;
+    *count = a[plan->NB];
+    if (!out) return FMMLM_OK;
+    if ((rc = get(plan->m2l_nfree, plan->NB, b)) || (rc = get(plan->m2l_src, a[plan->NB], c))) return rc;
+    for (int64_t t = 0; t < plan->NB; ++t)
+      for (int32_t k = a[t]; k < a[t + 1]; ++k) {
+        out[3 * k] = (int32_t)t;
+        out[3 * k + 1] = c[k];
+        out[3 * k + 2] = (k - a[t] < b[t]) ? 1 : 0;
+      }
+    return FMMLM_OK;
+  }
+  const int32_t* ptr = (which == 2) ? plan->p2p_ptr : plan->rp_ptr;
+  const int32_t* src = (which == 2) ? plan->p2p_src : plan->rp_src;
+  if ((rc = get(ptr, plan->nleaves + 1, a))) return rc;
+  *count = a[plan->nleaves];
+  if (!out) return FMMLM_OK;
+  if ((rc = get(plan->leaves, plan->nleaves, b)) || (rc = get(src, 2 * (int64_t)a[plan->nleaves], c))) return rc;
+  for (int64_t li = 0; li < plan->nleaves; ++li)
+    for (int32_t k = a[li]; k < a[li + 1]; ++k) {
+      out[3 * k] = b[li];
+      out[3 * k + 1] = c[2 * k];
+      out[3 * k + 2] = c[2 * k + 1];
+    }
+  return FMMLM_OK;
+}
+
 int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, const double* eps, int32_t lt,
                            int32_t ls, int32_t a, int32_t b, double S, int64_t npts, const double* rho,
                            const double* z, int32_t nmax, double* out, void* hip_stream) {

@@ -299,13 +299,15 @@ __global__ void reduce_loss_kernel(const float* __restrict__ lossp, int ntiles, 
 }
 
 // Adam (Kingma & Ba): m, v moving averages; c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t).
+// The weights 1 - beta come from the host, rounded once from their FP64 values
+// (1 - 0.999f in FP32 would be 1.3e-5 away from 0.001).
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t n, float lr, float beta1, float beta2, float c1,
-                            float c2, float eps) {
+                            float* __restrict__ v, int64_t n, float lr, float beta1, float beta2, float omb1,
+                            float omb2, float c1, float c2, float eps) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
-    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    const float mi = beta1 * m[i] + omb1 * gi;
+    const float vi = beta2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -457,6 +459,7 @@ int gpu_mlp_adam_steps(const MlpNet& net, int nsteps, const float* grads, const 
   for (int t = 1; t <= nsteps; ++t) {
     adam_kernel<<<256, 256, 0, st>>>(net.params, grads + (int64_t)(t - 1) * net.nparams, m, v, net.nparams,
                                      (float)lr[t - 1], (float)beta1, (float)beta2,
+                                     (float)(1.0 - beta1), (float)(1.0 - beta2),
                                      (float)(1.0 / (1.0 - std::pow(beta1, t))),
                                      (float)(1.0 / (1.0 - std::pow(beta2, t))), 1e-8f);
     FMM_HIP_TRY(hipGetLastError());
@@ -510,7 +513,8 @@ int gpu_mlp_train(const MlpNet& net, const int32_t* comp, const float* feat, con
     reduce_partials_kernel<<<256, 256, 0, st>>>(part, ntiles, net.nparams, grad);
     reduce_loss_kernel<<<1, 64, 0, st>>>(lossp, ntiles, 1.0 / ((double)B * net.nout), hist + (t - 1));
     adam_kernel<<<256, 256, 0, st>>>(net.params, grad, m, v, net.nparams, (float)lrt, (float)beta1,
-                                     (float)beta2, (float)(1.0 / (1.0 - std::pow(beta1, t))),
+                                     (float)beta2, (float)(1.0 - beta1), (float)(1.0 - beta2),
+                                     (float)(1.0 / (1.0 - std::pow(beta1, t))),
                                      (float)(1.0 / (1.0 - std::pow(beta2, t))), 1e-8f);
     FMM_HIP_TRY(hipGetLastError());
   }

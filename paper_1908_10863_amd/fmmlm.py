@@ -89,7 +89,7 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
            "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve",
            "fmm_layered_plan_general",
-           "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam"]
+           "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam", "fmm_layered_plan_lists"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -132,6 +132,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int64), vp, vp]
     L.fmm_layered_plan_tree.restype = ctypes.c_int
+    L.fmm_layered_plan_lists.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp]
+    L.fmm_layered_plan_lists.restype = ctypes.c_int
     L.fmm_layered_sommerfeld.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp]
@@ -299,6 +301,16 @@ class Plan:
         perm = np.zeros(n.value, np.int64)
         check(lib().fmm_layered_plan_tree(self._h, t, None, None, None, _ptr(keys), _ptr(perm)))
         return lay.value, side.value, keys, perm
+
+    def lists(self, which):
+        """Interaction-list table `which` (0 boxes, 1 M2L, 2 P2P free, 3 P2P reaction) as an
+        int32 array (see fmm_layered_plan_lists)."""
+        n = ctypes.c_int64()
+        check(lib().fmm_layered_plan_lists(self._h, which, ctypes.byref(n), None))
+        cols = 4 if which == 0 else 3
+        out = np.zeros((n.value, cols), np.int32)
+        check(lib().fmm_layered_plan_lists(self._h, which, ctypes.byref(n), _ptr(out)))
+        return out
 
     def profile_begin(self, max_evals):
         check(lib().fmm_layered_profile_begin(self._h, max_evals))

@@ -134,9 +134,10 @@ def test_sommerfeld_three_layer_tables(dev, F, oracle_mod, nmax):
 
 
 # ---------------------------------------------------------------- tree
-@pytest.mark.parametrize("cfg,n", [(0, None), (1, 20000)])
+@pytest.mark.parametrize("cfg,n", [(0, None), (1, 20000), (2, None)])
 def test_tree_keys_bit_exact(dev, F, oracle_mod, cfg, n):
     from paper_1908_10863_amd import workloads as W
+    # the last case is the benchmark's N = 1,048,576 (hundreds of radix-sort tiles per tree)
     _say(f"tree keys cfg={cfg}")
     w = W.config(cfg, n=n)
     plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=4, leaf_cap=w["leaf_cap"])
@@ -179,9 +180,14 @@ def test_config1_p8_full_oracle(dev, F, oracle_mod):
     phi_r, _ = _run(F, w, 8, dev, parts=2)
     phi, _ = _run(F, w, 8, dev, parts=3)
     ef, er, et = relerr(phi_f, ref_f), relerr(phi_r, ref_r), relerr(phi, ref_f + ref_r)
-    _say(f"  free {ef:.3e} reaction {er:.3e} total {et:.3e} stats {st}")
-    # truncation level at p = 8 (the reaction part is ~5x smaller than the free part)
-    assert ef < 5e-6 and er < 2e-5 and et < 5e-6
+    nf, nr = np.linalg.norm(ref_f), np.linalg.norm(ref_r)
+    _say(f"  free {ef:.3e} reaction {er:.3e} total {et:.3e} (absolute {ef * nf:.3e}, {er * nr:.3e}) stats {st}")
+    # Truncation at p = 8, MAC 6 (measured 1.63e-6 free, 1.81e-6 total).  Both parts pass
+    # through the same expansions at the same p and MAC, so their absolute errors are
+    # alike; the reaction part is held to the free part's bound in absolute terms
+    # (its norm is 1/4.86 of the free part's, so its relative error is ~5x larger).
+    assert ef < 5e-6 and et < 5e-6
+    assert er * nr < 5e-6 * nf
     np.testing.assert_allclose(phi_f + phi_r, phi, rtol=0, atol=1e-12 * np.abs(phi).max())
 
 
@@ -332,6 +338,33 @@ def test_charges_on_one_vertical_line(dev, F, oracle_mod):
     assert e < 1e-9
 
 
+def test_charges_on_one_vertical_line_fp32(dev, F, oracle_mod):
+    """The same input in the FP32 form at the benchmark's settings (p = 10, mac_d2 = 4): a
+    documented limit of that form.  The closest pairs are about 4e-6 apart, below the
+    resolution of a leaf-relative FP32 coordinate difference on these deep leaves, and
+    mac_d2 = 4 leaves a worst-case reaction truncation near 1e-4 for boxes on one axis;
+    the test records the error and holds it to the level measured when the limit was
+    documented (1.6e-4), not to the form's 1e-5 for uniform boxes."""
+    import torch
+    rng = np.random.default_rng(81)
+    n = 1500
+    lay = np.repeat([0, 1, 2], n // 3).astype(np.int32)
+    zr = {0: (0.1, 1.1), 1: (-0.9, -0.1), 2: (-2.0, -1.1)}
+    z = np.array([rng.uniform(*zr[int(v)]) for v in lay])
+    x = np.zeros(n)
+    q = rng.uniform(-1, 1, n)
+    out = {}
+    for parts in (1, 2, 3):
+        ref = oracle_mod.potential(D3, E3, x, x, z, lay, q, method="image3", parts=parts)
+        pl = F.Plan(D3, E3, x, x, z, lay, p=10, leaf_cap=20, precision=F.FMMLM_FP32_COMPENSATED, mac_d2=4)
+        phi = pl.eval(torch.tensor(q, device=dev), parts=parts).cpu().numpy()
+        pl.close()
+        out[parts] = relerr(phi, ref)
+    _say(f"  vertical line, FP32 form p=10 mac 4: free {out[1]:.2e} reaction {out[2]:.2e} total {out[3]:.2e}")
+    assert out[3] < 3e-4
+    assert out[1] < 3e-4 and out[2] < 3e-4
+
+
 def test_high_contrast_medium(dev, F, oracle_mod):
     """eps = (1, 80, 1): reflections of magnitude 0.975 give the density sharp
     resonances along the imaginary axis.  The contour form's integrals stay within
@@ -412,7 +445,8 @@ def test_near_field_kernel_values(dev, F, oracle_mod, d, eps):
                         got = F.sommerfeld(d, eps, lt, ls, a, b, 1.0, rhos, np.full(len(rhos), zeta), 0)[:, 0]
                         ref = np.array([4 * math.pi * oracle_mod.reaction_quad(d, eps, lt, ls, a, b, r, zeta)
                                         for r in rhos])
-                        np.testing.assert_allclose(got, ref, rtol=5e-10, atol=1e-13 * np.abs(ref).max())
+                        # GPU graded rule and oracle fixed rule agree to 2.4e-15 here (four layers)
+                        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
 
 
 def test_pure_near_field_matches_direct_sum(dev, F, oracle_mod):
@@ -479,11 +513,26 @@ def test_tiny_and_ragged_inputs(dev, F, oracle_mod):
     ]
     for x, y, z, lay, cap in cases:
         q = np.linspace(-1, 1, len(x)) + 0.3
-        plan = F.Plan(D3, E3, x, y, z, lay, p=12, leaf_cap=cap)
-        phi = plan.eval(torch.tensor(q, dtype=torch.float64, device=dev)).cpu().numpy()
         ref = oracle_mod.potential(D3, E3, x, y, z, lay, q)
-        assert relerr(phi, ref) < 1e-7
-        plan.close()
+        err = {}
+        for p in (8, 12):
+            plan = F.Plan(D3, E3, x, y, z, lay, p=p, leaf_cap=cap)
+            phi = plan.eval(torch.tensor(q, dtype=torch.float64, device=dev)).cpu().numpy()
+            st = plan.stats()
+            plan.close()
+            err[p] = np.abs(phi - ref) / np.abs(ref)
+            far = st["m2l_free_pairs"] + st["m2l_reaction_pairs"]
+        _say(f"  n={len(x)} cap={cap} M2L pairs {far}: p=8 {err[8]}, p=12 {err[12]}")
+        if far == 0:
+            # pure near field: nothing is truncated, only rounding remains
+            assert err[8].max() < 1e-13 and err[12].max() < 1e-13
+        else:
+            # element by element: truncation at p = 8 (measured 6.8e-8 on the one reaction
+            # M2L pair) and, from p = 8 to 12, at least the geometric decay (1/sqrt(2))^4 of
+            # eq. meerror's rate for boxes separated by mac_d2 = 6 ((a_s + a_t) / R <=
+            # sqrt(3) / sqrt(6)); points in leaves of their own keep rounding
+            assert err[8].max() < 1e-6
+            assert np.all(err[12] <= err[8] * 0.5 ** 2 + 1e-13)
 
 
 @pytest.mark.parametrize("cfg,p,tol", [(1, 12, 1e-7), (2, 10, 1e-6)])
