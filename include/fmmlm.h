@@ -482,6 +482,46 @@ int fmm_layered_surrogate_eval(fmmlm_surrogate_t s, int32_t lt, int32_t ls, int3
                                int64_t npts, const double* rho, const double* z, int32_t nmax, double* out,
                                int32_t* used, void* hip_stream);
 
+/* ---- pre-computed tables for the initial values (the Remark after Table 3.1)
+ *
+ * The table form serves the same 4p+1 initial values S^n I_{n,0}, S^n I_{n,1}
+ * (and the near-field kernels I_00) as the learned form, with the network's
+ * part 3 replaced by 2-D tables: per component, what the leading term and the
+ * ladder leave, times 0.7^n R2^{n+1} (output units as for the network, with
+ * yscale 1), is tabulated at the kTabK = 12 Chebyshev points of the first kind
+ * x_k = cos((2k + 1) pi / 24), k = 0..11, of each of npr x npz equal panels
+ * over [0, rho_max] x [0, zeta_max] (node (a, b) of panel (i, j) at
+ * rho = (i + (1 + x_a) / 2) rho_max / npr, zeta = (j + (1 + x_b) / 2) zeta_max / npz),
+ * filled by the GPU quadrature when the form is created, and interpolated by
+ * the barycentric formula (tensor product of degree 11 in each variable).
+ * Panels are no wider than the thinnest finite layer (4..48 per direction).
+ * The handle is a fmmlm_surrogate_t: a plan takes it through opts.surrogate,
+ * fmm_layered_surrogate_eval and _destroy accept it, the network calls
+ * (train, params, grad, forward, adam, samples) return FMMLM_EUNSUPPORTED.
+ * Needs at least two interfaces.  Errors as for fmm_layered_surrogate_create,
+ * FMMLM_ENOMEM for the tables' device memory.
+ */
+int fmm_layered_tables_create(int32_t n_interfaces, const double* z_interfaces, const double* eps, int32_t p,
+                              double rho_max, double zeta_max, void* hip_stream, fmmlm_surrogate_t* out);
+
+/* The same over a plan's medium, p and (rho, zeta) domain (as for
+ * fmm_layered_surrogate_create_for_plan). */
+int fmm_layered_tables_create_for_plan(fmmlm_plan_t plan, void* hip_stream, fmmlm_surrogate_t* out);
+
+/* Grid of a table form (panels per direction), the tables' device bytes and the
+ * seconds it took to create them (ladder fit and quadrature at the nodes); any
+ * output may be NULL.  FMMLM_EINVAL for a network handle. */
+int fmm_layered_tables_info(fmmlm_surrogate_t s, int32_t* npr, int32_t* npz, int64_t* bytes, double* seconds);
+
+/* The table form's interpolation alone, on given node values (tests): nodes
+ * (host) [npr * npz][nout][12 * 12] in the layout above (panel i * npz + j,
+ * node a * 12 + b), points rho, zeta (host [npts], inside the box), out (host)
+ * [npts][nout].  Exact for polynomials of degree <= 11 in each variable on each
+ * panel.  Errors: FMMLM_EINVAL, FMMLM_ENOMEM, FMMLM_EDEVICE. */
+int fmm_layered_interp2d(int32_t npr, int32_t npz, double rho_max, double zeta_max, int32_t nout,
+                         const double* nodes, int64_t npts, const double* rho, const double* zeta, double* out,
+                         void* hip_stream);
+
 /*
  * Leading term of a reaction density as k -> infinity (eq. densityasymptotic):
  * sigma^{ab}_{lt,ls}(k) = sinf e^{-k zinf} (1 + O(e^{-2 k dmin})), dmin the

@@ -1141,7 +1141,10 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   if (!B.tasks.empty()) {
     FMM_HIP_TRY(hipMalloc(&tables, B.tasks.size() * (size_t)P->ng * sizeof(double)));
     const auto ts = std::chrono::steady_clock::now();
-    if (sur) {
+    if (sur && sur->kind == 1) {
+      rc = gpu_table_tasks(P->medium, comps, smap, sur->d_lad, sur->dm, sur->tg, sur->d_tab, sur->nmax, B.tasks,
+                           2 * p, tables, &P->stats.surrogate_tasks, st, nullptr);
+    } else if (sur) {
       rc = gpu_surrogate_tables(P->medium, comps, smap, sur->d_lad, sur->dm, B.tasks, 2 * p, sur->net, tables,
                                 &P->stats.surrogate_tasks, st, nullptr);
     } else {
@@ -1190,7 +1193,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     FMM_HIP_TRY(hipMemcpyAsync(ds, rp_s.data(), npairs * 4, hipMemcpyHostToDevice, st));
     FMM_HIP_TRY(hipMemcpyAsync(dc, rp_c.data(), npairs * 4, hipMemcpyHostToDevice, st));
     const auto ts = std::chrono::steady_clock::now();
-    if (sur) {
+    if (sur && sur->kind == 1) {
+      int64_t nfb = 0;
+      rc = gpu_table_nearfield(P->medium, comps, smap, sur->d_lad, sur->dm, sur->tg, sur->d_tab, 2 * sur->nmax + 1,
+                               dt, ds, dc, npairs, P->px, P->py, P->ph, P->rp_val, &nfb, st);
+      P->stats.surrogate_pairs = npairs - nfb;
+    } else if (sur) {
       int64_t nfb = 0;
       rc = gpu_surrogate_nearfield(P->medium, comps, smap, sur->d_lad, sur->dm, dt, ds, dc, npairs, P->px,
                                    P->py, P->ph, sur->net, P->rp_val, &nfb, st);
@@ -1994,16 +2002,155 @@ int fmm_layered_surrogate_create_for_plan(fmmlm_plan_t plan, uint64_t seed, fmml
                                       2.0 * plan->W, seed, out);
 }
 
+int fmm_layered_tables_create(int32_t n_interfaces, const double* z_interfaces, const double* eps, int32_t p,
+                              double rho_max, double zeta_max, void* hip_stream, fmmlm_surrogate_t* out) {
+  if (!out) return FMMLM_EINVAL;
+  *out = nullptr;
+  if (!z_interfaces || !eps || p < 1 || p > FMMLM_PMAX) return FMMLM_EINVAL;
+  if (!(rho_max > 0.0) || !(zeta_max > 0.0) || !std::isfinite(rho_max) || !std::isfinite(zeta_max))
+    return FMMLM_EINVAL;
+  if (n_interfaces < 1 || n_interfaces > kMaxL) return FMMLM_EINVAL;
+  std::vector<double> dv, ev;
+  int rc;
+  if ((rc = fetch(z_interfaces, n_interfaces, dv))) return rc;
+  if ((rc = fetch(eps, n_interfaces + 1, ev))) return rc;
+  if ((rc = validate_medium(n_interfaces, dv, ev))) return rc;
+  if (n_interfaces < 2) {
+    set_last_error("the table form needs at least two interfaces");
+    return FMMLM_EUNSUPPORTED;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  fmmlm_surrogate_s* S = new (std::nothrow) fmmlm_surrogate_s();
+  if (!S) return FMMLM_ENOMEM;
+  const int L = n_interfaces;
+  S->kind = 1;
+  S->L = L;
+  S->d = dv;
+  S->eps = ev;
+  S->medium = make_medium(L, dv.data(), ev.data());
+  S->p = p;
+  S->nmax = 2 * p;
+  double dmin = 0.0;
+  for (int i = 1; i < L; ++i) {
+    const double t = dv[i - 1] - dv[i];
+    if (dmin == 0.0 || t < dmin) dmin = t;
+  }
+  // values in the remainder's own unit (yscale 1)
+  S->dm = SurrogateDomain{rho_max, zeta_max, dmin, 2.0 * dmin, 1.0};
+  std::vector<std::pair<int, int>> sides;
+  for (int l = 0; l <= L; ++l)
+    for (int side = 1; side <= 2; ++side) {
+      if ((side == 1 && l > L - 1) || (side == 2 && l < 1)) continue;
+      sides.push_back({l, side});
+    }
+  for (auto& t : sides)
+    for (auto& u : sides) S->comps.push_back(make_comp(S->medium, t.first, u.first, t.second, u.second));
+  // panels no wider than the thinnest layer: the remainder's nearest singularity
+  // (the first image beyond the leading one) lies at least 2 dmin off the real
+  // (rho, zeta) domain, so each panel's Chebyshev interpolant converges fast
+  auto panels = [&](double ext) {
+    const int n = (int)std::ceil(ext / dmin - 1e-9);
+    return std::min(std::max(n, 4), 48);
+  };
+  S->tg.npr = panels(rho_max);
+  S->tg.npz = panels(zeta_max);
+  S->tg.hr = rho_max / S->tg.npr;
+  S->tg.hz = zeta_max / S->tg.npz;
+  (void)hipGetDevice(&S->device);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nout = 2 * S->nmax + 1;
+  const size_t nval = S->comps.size() * (size_t)S->tg.npr * S->tg.npz * nout * kTabK * kTabK;
+  hipError_t e = hipMalloc(&S->d_tab, nval * sizeof(double));
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_ENOMEM;
+  }
+  if (rc == FMMLM_OK) rc = fit_ladders(S, st);
+  if (rc == FMMLM_OK) rc = gpu_table_fill(S->medium, S->comps, S->d_lad, S->dm, S->tg, S->nmax, S->d_tab, st);
+  if (rc) {
+    hipFree(S->d_tab);
+    hipFree(S->d_lad);
+    delete S;
+    return rc;
+  }
+  S->fill_seconds = seconds_since(t0);
+  *out = S;
+  return FMMLM_OK;
+}
+
+int fmm_layered_tables_create_for_plan(fmmlm_plan_t plan, void* hip_stream, fmmlm_surrogate_t* out) {
+  if (!plan || !out) return FMMLM_EINVAL;
+  return fmm_layered_tables_create(plan->L, plan->d.data(), plan->eps.data(), plan->p, std::sqrt(2.0) * plan->W,
+                                   2.0 * plan->W, hip_stream, out);
+}
+
+int fmm_layered_tables_info(fmmlm_surrogate_t s, int32_t* npr, int32_t* npz, int64_t* bytes, double* seconds) {
+  if (!s || s->kind != 1) return FMMLM_EINVAL;
+  if (npr) *npr = s->tg.npr;
+  if (npz) *npz = s->tg.npz;
+  if (bytes)
+    *bytes = (int64_t)(s->comps.size() * (size_t)s->tg.npr * s->tg.npz * (2 * s->nmax + 1) * kTabK * kTabK *
+                       sizeof(double));
+  if (seconds) *seconds = s->fill_seconds;
+  return FMMLM_OK;
+}
+
+int fmm_layered_interp2d(int32_t npr, int32_t npz, double rho_max, double zeta_max, int32_t nout,
+                         const double* nodes, int64_t npts, const double* rho, const double* zeta, double* out,
+                         void* hip_stream) {
+  if (npr < 1 || npz < 1 || npr > 4096 || npz > 4096 || nout < 1 || nout > 1024 || !nodes || npts < 1 || !rho ||
+      !zeta || !out || !(rho_max > 0.0) || !(zeta_max > 0.0))
+    return FMMLM_EINVAL;
+  for (int64_t i = 0; i < npts; ++i)
+    if (!(rho[i] >= 0.0 && rho[i] <= rho_max && zeta[i] >= 0.0 && zeta[i] <= zeta_max)) return FMMLM_EINVAL;
+  TableGrid g;
+  g.npr = npr;
+  g.npz = npz;
+  g.hr = rho_max / npr;
+  g.hz = zeta_max / npz;
+  const size_t nn = (size_t)npr * npz * nout * kTabK * kTabK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double *dn = nullptr, *dp = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dn, nn * sizeof(double)));
+  if (hipMalloc(&dp, (size_t)npts * (2 + nout) * sizeof(double)) != hipSuccess) {
+    hipFree(dn);
+    set_last_error("fmm_layered_interp2d: allocation failed");
+    return FMMLM_ENOMEM;
+  }
+  int rc = FMMLM_OK;
+  hipError_t e = hipMemcpy(dn, nodes, nn * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dp, rho, npts * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dp + npts, zeta, npts * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e));
+    rc = FMMLM_EDEVICE;
+  }
+  if (rc == FMMLM_OK) rc = gpu_interp2d(g, nout, dn, npts, dp, dp + npts, dp + 2 * npts, st);
+  if (rc == FMMLM_OK && hipStreamSynchronize(st) != hipSuccess) rc = FMMLM_EDEVICE;
+  if (rc == FMMLM_OK) {
+    e = hipMemcpy(out, dp + 2 * npts, (size_t)npts * nout * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_last_error(hipGetErrorString(e));
+      rc = FMMLM_EDEVICE;
+    }
+  }
+  hipFree(dn);
+  hipFree(dp);
+  return rc;
+}
+
 int fmm_layered_surrogate_destroy(fmmlm_surrogate_t s) {
   if (!s) return FMMLM_EINVAL;
   hipFree(s->net.params);
   hipFree(s->d_lad);
+  hipFree(s->d_tab);
   delete s;
   return FMMLM_OK;
 }
 
 int fmm_layered_surrogate_train(fmmlm_surrogate_t s, const fmmlm_train_opts* opts, void* hip_stream,
                                 fmmlm_train_report* rep) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s) return FMMLM_EINVAL;
   fmmlm_train_opts o;
   fmmlm_default_train_opts(&o);
@@ -2075,6 +2222,7 @@ int fmm_layered_surrogate_train(fmmlm_surrogate_t s, const fmmlm_train_opts* opt
 }
 
 int fmm_layered_surrogate_params(fmmlm_surrogate_t s, float* get, const float* set, int64_t* n) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s) return FMMLM_EINVAL;
   if (n) *n = s->net.nparams;
   if (get) FMM_HIP_TRY(hipMemcpy(get, s->net.params, s->net.nparams * sizeof(float), hipMemcpyDeviceToHost));
@@ -2084,6 +2232,7 @@ int fmm_layered_surrogate_params(fmmlm_surrogate_t s, float* get, const float* s
 
 int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
                                const float* target, double* loss, float* grad, void* hip_stream) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !feat || !target || !loss || !grad) return FMMLM_EINVAL;
   for (int64_t i = 0; i < n; ++i)
     if (comp[i] < 0 || comp[i] >= s->net.ncomp) return FMMLM_EINVAL;
@@ -2120,6 +2269,7 @@ int fmm_layered_surrogate_grad(fmmlm_surrogate_t s, int64_t n, const int32_t* co
 
 int fmm_layered_surrogate_forward(fmmlm_surrogate_t s, int64_t n, const int32_t* comp, const float* feat,
                                   float* out, void* hip_stream) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !feat || !out) return FMMLM_EINVAL;
   for (int64_t i = 0; i < n; ++i)
     if (comp[i] < 0 || comp[i] >= s->net.ncomp) return FMMLM_EINVAL;
@@ -2157,6 +2307,7 @@ int fmm_layered_surrogate_forward(fmmlm_surrogate_t s, int64_t n, const int32_t*
 
 int fmm_layered_surrogate_adam(fmmlm_surrogate_t s, int32_t nsteps, const float* grads, const double* lr,
                                float* params_out, void* hip_stream) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s || nsteps < 1 || nsteps > 64 || !grads || !lr) return FMMLM_EINVAL;
   for (int t = 0; t < nsteps; ++t)
     if (!std::isfinite(lr[t]) || !(lr[t] > 0.0)) return FMMLM_EINVAL;
@@ -2190,6 +2341,7 @@ int fmm_layered_surrogate_adam(fmmlm_surrogate_t s, int32_t nsteps, const float*
 
 int fmm_layered_surrogate_samples(fmmlm_surrogate_t s, int64_t n, uint64_t seed, int32_t* comp, double* rho,
                                   double* zeta, float* feat, float* target, void* hip_stream) {
+  if (s && s->kind != 0) return FMMLM_EUNSUPPORTED;  // a table form has no network
   if (!s || n < 1 || n > ((int64_t)1 << 24) || !comp || !rho || !zeta || !feat || !target) return FMMLM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int nout = s->net.nout;
@@ -2245,7 +2397,10 @@ int fmm_layered_surrogate_eval(fmmlm_surrogate_t s, int32_t lt, int32_t ls, int3
   const size_t per = ncoef(nmax);
   FMM_HIP_TRY(hipMalloc(&d, npts * per * sizeof(double)));
   int64_t nu = 0;
-  int rc = gpu_surrogate_tables(s->medium, comps, smap, s->d_lad, s->dm, tasks, nmax, s->net, d, &nu, st, used);
+  int rc = (s->kind == 1)
+               ? gpu_table_tasks(s->medium, comps, smap, s->d_lad, s->dm, s->tg, s->d_tab, s->nmax, tasks, nmax, d,
+                                 &nu, st, used)
+               : gpu_surrogate_tables(s->medium, comps, smap, s->d_lad, s->dm, tasks, nmax, s->net, d, &nu, st, used);
   if (rc == FMMLM_OK) {
     hipError_t e = hipMemcpy(out, d, npts * per * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {

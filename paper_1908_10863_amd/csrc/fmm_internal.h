@@ -297,6 +297,12 @@ constexpr int kMlpH = 128;   // hidden width
 constexpr int kLadder = 8;   // closed-form rungs sum_j c_j e^{-k j delta} of the density's remainder
 constexpr double kSurDecay = 0.7;  // network output j carries the weight kSurDecay^{n_j}
 constexpr int kMlpF = 4;     // continuous input features
+// table form: Chebyshev points per panel and direction, panel grid over the domain
+constexpr int kTabK = 12;
+struct TableGrid {
+  int npr = 0, npz = 0;      // panels in rho and in zeta
+  double hr = 0.0, hz = 0.0; // panel sizes: rho_max / npr, zeta_max / npz
+};
 struct MlpNet {
   int ncomp = 0, nout = 0;   // components (one-hot input), outputs
   float* params = nullptr;   // device, flat: E A b1 W2 b2 W3 b3 W4 b4 (W[k][j]: input k -> output j)
@@ -327,6 +333,20 @@ int gpu_surrogate_nearfield(const Medium& md, const std::vector<CompInfo>& comps
                             const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
                             int64_t npairs, const double* px, const double* py, const double* ph,
                             const MlpNet& net, double* d_val, int64_t* n_fallback, hipStream_t st);
+
+int gpu_table_fill(const Medium& md, const std::vector<CompInfo>& comps, const double* d_lad,
+                   const SurrogateDomain& dm, const TableGrid& g, int nmax, double* d_tab, hipStream_t st);
+int gpu_table_tasks(const Medium& md, const std::vector<CompInfo>& comps, const std::vector<int32_t>& smap,
+                    const double* d_lad, const SurrogateDomain& dm, const TableGrid& g, const double* d_tab,
+                    int ynmax, const std::vector<SommTask>& tasks, int nmax, double* d_out, int64_t* n_used,
+                    hipStream_t st, int32_t* h_used);
+int gpu_table_nearfield(const Medium& md, const std::vector<CompInfo>& comps, const std::vector<int32_t>& smap,
+                        const double* d_lad, const SurrogateDomain& dm, const TableGrid& g, const double* d_tab,
+                        int nout, const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp, int64_t npairs,
+                        const double* px, const double* py, const double* ph, double* d_val, int64_t* n_fallback,
+                        hipStream_t st);
+int gpu_interp2d(const TableGrid& g, int nout, const double* d_nodes, int64_t n, const double* d_rho,
+                 const double* d_zeta, double* d_out, hipStream_t st);
 
 // fmm.hip
 int gpu_build_ops(fmmlm_plan_s* P, const std::vector<int>& free_off,
@@ -378,6 +398,11 @@ struct fmmlm_surrogate_s {
   double* d_lad = nullptr;             // device copy
   double ladder_fit = 0.0;             // largest weighted residual of the ladder fits
   int device = 0;
+  // table form (kind 1): the remainder tabulated instead of learned
+  int kind = 0;                        // 0 network, 1 tables
+  fmmlm::TableGrid tg;
+  double* d_tab = nullptr;             // [component][panel][output][kTabK^2]
+  double fill_seconds = 0.0;           // filling the tables by the quadrature
 };
 
 #define FMM_HIP_TRY(expr)                                                      \

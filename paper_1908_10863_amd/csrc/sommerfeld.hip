@@ -499,6 +499,38 @@ __global__ void surrogate_task_features_kernel(const CompInfo* __restrict__ comp
   feat[t] = f;
 }
 
+// Initial values of a task inside the learned form's domain: the leading term
+// and the ladder (lad: this component's rungs) in closed form plus the
+// remainder S^n yscale rem(j) / (kSurDecay^n R2^{n+1}) for m = 0, 1, where
+// rem(j) is output j in output units (j = n for m = 0, ynmax + n for m = 1).
+template <class Rem>
+__device__ void learned_task_values(const CompInfo& c, const double* __restrict__ lad, const SurrogateDomain& dm,
+                                    const SommTask& tk, int nmax, int ynmax, Rem rem, double* i0, double* i1) {
+  for (int n = 0; n <= nmax; ++n) i0[n] = i1[n] = 0.0;
+  double* o1 = tk.rho > 0.0 ? i1 : nullptr;
+  image_values(c.sinf, tk.S, tk.rho, tk.z + c.zinf, nmax, i0, o1);
+  ladder_values(lad, dm.delta, 1.0, tk.S, tk.rho, tk.z + c.zinf, nmax, i0, o1);
+  const double Z2 = tk.z + c.zinf + 2.0 * dm.dmin;
+  const double R2 = sqrt(tk.rho * tk.rho + Z2 * Z2);
+  double pw = dm.yscale / R2;  // yscale S^n / (kSurDecay^n R2^{n+1})
+  for (int n = 0; n <= nmax; ++n) {
+    i0[n] += pw * rem(n);
+    if (n >= 1 && tk.rho > 0.0) i1[n] += pw * rem(ynmax + n);
+    pw *= tk.S / (R2 * kSurDecay);
+  }
+}
+
+// The learned form's near-field value I_00 (S = 1) without the 1/(4 pi): the
+// closed-form parts plus yscale rem0 / R2.
+__device__ inline double learned_pair_value(const CompInfo& c, const double* __restrict__ lad,
+                                            const SurrogateDomain& dm, double rho, double zeta, double rem0) {
+  double v0 = 0.0;
+  image_values(c.sinf, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
+  ladder_values(lad, dm.delta, 1.0, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
+  const double Z2 = zeta + c.zinf + 2.0 * dm.dmin;
+  return v0 + dm.yscale * rem0 / sqrt(rho * rho + Z2 * Z2);
+}
+
 // S^n I_{n,m} for a task: the leading term and the ladder in closed form plus
 // the network's remainder S^n yscale y_j / (kSurDecay^n R2^{n+1}) (FP32
 // network, FP64 here) for m = 0, 1; the quadrature when (rho, z) lies outside
@@ -516,20 +548,9 @@ __global__ void surrogate_table_kernel(Medium md, const CompInfo* __restrict__ c
   double i0[kMaxN], i1[kMaxN];
   const bool net = surrogate_in_domain(dm, tk.rho, tk.z);
   if (net) {
-    for (int n = 0; n <= nmax; ++n) i0[n] = i1[n] = 0.0;
-    double* o1 = tk.rho > 0.0 ? i1 : nullptr;
-    image_values(c.sinf, tk.S, tk.rho, tk.z + c.zinf, nmax, i0, o1);
-    ladder_values(lad + (int64_t)scomp[t] * kLadder, dm.delta, 1.0, tk.S, tk.rho, tk.z + c.zinf, nmax, i0,
-                  o1);
-    const double Z2 = tk.z + c.zinf + 2.0 * dm.dmin;
-    const double R2 = sqrt(tk.rho * tk.rho + Z2 * Z2);
     const float* yy = y + (int64_t)t * ldy;
-    double pw = dm.yscale / R2;  // yscale S^n / (kSurDecay^n R2^{n+1})
-    for (int n = 0; n <= nmax; ++n) {
-      i0[n] += pw * (double)yy[n];
-      if (n >= 1 && tk.rho > 0.0) i1[n] += pw * (double)yy[ynmax + n];
-      pw *= tk.S / (R2 * kSurDecay);
-    }
+    learned_task_values(c, lad + (int64_t)scomp[t] * kLadder, dm, tk, nmax, ynmax,
+                        [&](int j) { return (double)yy[j]; }, i0, i1);
   } else {
     Scatter sc;
     local_coeffs(md, sc);
@@ -582,11 +603,7 @@ __global__ void surrogate_nearfield_kernel(Medium md, const CompInfo* __restrict
   const CompInfo c = comps[cmp[i]];
   double v0;
   if (surrogate_in_domain(dm, rho, zeta)) {
-    v0 = 0.0;
-    image_values(c.sinf, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
-    ladder_values(lad + (int64_t)scomp[i] * kLadder, dm.delta, 1.0, 1.0, rho, zeta + c.zinf, 0, &v0, nullptr);
-    const double Z2 = zeta + c.zinf + 2.0 * dm.dmin;
-    v0 += dm.yscale * (double)y[i * ldy] / sqrt(rho * rho + Z2 * Z2);
+    v0 = learned_pair_value(c, lad + (int64_t)scomp[i] * kLadder, dm, rho, zeta, (double)y[i * ldy]);
   } else {
     Scatter sc;
     local_coeffs(md, sc);
@@ -594,6 +611,175 @@ __global__ void surrogate_nearfield_kernel(Medium md, const CompInfo* __restrict
     atomicAdd(nfallback, 1ull);
   }
   val[i] = v0 * (1.0 / (4.0 * 3.14159265358979323846));
+}
+
+// ---------------------------------------------------------------- table form
+// Pre-computed 2-D tables for the initial values (the Remark after Table 3.1):
+// per component, the remainder the network would learn (what the leading term
+// and the ladder leave, times kSurDecay^n R2^{n+1}, a smooth O(1) function of
+// (rho, zeta)) is tabulated on a grid of npr x npz panels over the domain, at
+// kTabK Chebyshev points of the first kind per panel and direction, and
+// interpolated by the barycentric formula (tensor product, degree kTabK - 1 in
+// rho and in zeta: exact on polynomials of that degree).  Layout: component,
+// panel (pr * npz + pz), output j, node (a * kTabK + b; a in rho, b in zeta).
+__constant__ double c_chx[kTabK];  // cos((2k + 1) pi / (2 kTabK))
+__constant__ double c_chw[kTabK];  // barycentric weights (-1)^k sin((2k + 1) pi / (2 kTabK))
+
+// Lagrange basis values l[k] at x in [-1, 1] (barycentric formula; exact at nodes)
+__device__ inline void cheb_lagrange(double x, double* l) {
+  int hit = -1;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kTabK; ++k) {
+    const double dx = x - c_chx[k];
+    if (dx == 0.0) hit = k;
+    const double t = c_chw[k] / (dx == 0.0 ? 1.0 : dx);
+    l[k] = t;
+    s += t;
+  }
+  if (hit >= 0) {
+#pragma unroll
+    for (int k = 0; k < kTabK; ++k) l[k] = (k == hit) ? 1.0 : 0.0;
+    return;
+  }
+  const double is = 1.0 / s;
+#pragma unroll
+  for (int k = 0; k < kTabK; ++k) l[k] *= is;
+}
+
+// panel of (rho, zeta) (clamped to the grid) and the basis values in both directions
+__device__ inline int table_cell(const TableGrid& g, double rho, double zeta, double* lr, double* lz) {
+  int pr = (int)(rho / g.hr), pz = (int)(zeta / g.hz);
+  pr = pr < 0 ? 0 : (pr >= g.npr ? g.npr - 1 : pr);
+  pz = pz < 0 ? 0 : (pz >= g.npz ? g.npz - 1 : pz);
+  cheb_lagrange(2.0 * (rho - pr * g.hr) / g.hr - 1.0, lr);
+  cheb_lagrange(2.0 * (zeta - pz * g.hz) / g.hz - 1.0, lz);
+  return pr * g.npz + pz;
+}
+
+// output j of a panel block [nout][kTabK * kTabK]
+__device__ inline double table_value(const double* __restrict__ blk, int j, const double* lr, const double* lz) {
+  const double* f = blk + (int64_t)j * kTabK * kTabK;
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < kTabK; ++a) {
+    double r = 0.0;
+#pragma unroll
+    for (int b = 0; b < kTabK; ++b) r += lz[b] * f[a * kTabK + b];
+    acc += lr[a] * r;
+  }
+  return acc;
+}
+
+// One thread per (component, panel, node): the remainder's scaled initial values
+// by the quadrature (the same targets as the network's training samples).
+__global__ void table_fill_kernel(Medium md, const CompInfo* __restrict__ comps, int ncomp,
+                                  const double* __restrict__ lad, SurrogateDomain dm, TableGrid g, int nmax,
+                                  double* __restrict__ tab) {
+  constexpr int KK = kTabK * kTabK;
+  const int64_t per = (int64_t)g.npr * g.npz * KK;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * ncomp) return;
+  const int c = (int)(i / per);
+  const int64_t r = i % per;
+  const int cell = (int)(r / KK), ab = (int)(r % KK);
+  const int pr = cell / g.npz, pz = cell % g.npz, a = ab / kTabK, b = ab % kTabK;
+  const double rho = (pr + 0.5 + 0.5 * c_chx[a]) * g.hr;
+  const double zeta = (pz + 0.5 + 0.5 * c_chx[b]) * g.hz;
+  Scatter sc;
+  local_coeffs(md, sc);
+  const CompInfo ci = comps[c];
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double i0[kMaxN], i1[kMaxN];
+  initial_values(md, sc, ci, 1.0, rho, zeta, nmax, i0, i1, false);
+  ladder_values(lad + (int64_t)c * kLadder, dm.delta, -1.0, 1.0, rho, zeta + ci.zinf, nmax, i0, i1);
+  const double Z2 = zeta + ci.zinf + 2.0 * dm.dmin;
+  const double R2 = sqrt(rho * rho + Z2 * Z2);
+  const int nout = 2 * nmax + 1;
+  double* blk = tab + ((int64_t)c * g.npr * g.npz + cell) * nout * KK;
+  double pw = R2 / dm.yscale;  // kSurDecay^n R2^{n+1} / yscale
+  for (int n = 0; n <= nmax; ++n) {
+    blk[(int64_t)n * KK + ab] = i0[n] * pw;
+    if (n >= 1) blk[(int64_t)(nmax + n) * KK + ab] = i1[n] * pw;
+    pw *= R2 * kSurDecay;
+  }
+}
+
+// S^n I_{n,m} of tasks through the tables (quadrature outside the domain), then eq. recurrence.
+__global__ void table_task_kernel(Medium md, const CompInfo* __restrict__ comps, const int32_t* __restrict__ smap,
+                                  const double* __restrict__ lad, SurrogateDomain dm, TableGrid g,
+                                  const double* __restrict__ tab, int ynmax, const SommTask* __restrict__ tasks,
+                                  int ntask, int nmax, double* __restrict__ out, int32_t* __restrict__ used) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const SommTask tk = tasks[t];
+  const CompInfo c = comps[tk.comp];
+  constexpr int kMaxN = 2 * kPMax + 1;
+  double i0[kMaxN], i1[kMaxN];
+  const bool in = surrogate_in_domain(dm, tk.rho, tk.z);
+  if (in) {
+    const int sc = smap[tk.comp];
+    double lr[kTabK], lz[kTabK];
+    const int cell = table_cell(g, tk.rho, tk.z, lr, lz);
+    const double* blk = tab + ((int64_t)sc * g.npr * g.npz + cell) * (2 * ynmax + 1) * kTabK * kTabK;
+    learned_task_values(c, lad + (int64_t)sc * kLadder, dm, tk, nmax, ynmax,
+                        [&](int j) { return table_value(blk, j, lr, lz); }, i0, i1);
+  } else {
+    Scatter scat;
+    local_coeffs(md, scat);
+    initial_values(md, scat, c, tk.S, tk.rho, tk.z, nmax, i0, i1);
+  }
+  double* o = out + (int64_t)t * ncoef(nmax);
+  for (int n = 0; n <= nmax; ++n) {
+    o[cidx(n, 0)] = i0[n];
+    if (n >= 1) o[cidx(n, 1)] = i1[n];
+  }
+  recurrence_fill(tk.S, tk.rho, nmax, o);
+  if (used) used[t] = in ? 1 : 0;
+}
+
+// Reaction near field through the tables (output 0, I_00); quadrature outside the domain.
+__global__ void table_nearfield_kernel(Medium md, const CompInfo* __restrict__ comps,
+                                       const int32_t* __restrict__ smap, const double* __restrict__ lad,
+                                       SurrogateDomain dm, TableGrid g, const double* __restrict__ tab, int nout,
+                                       const int32_t* __restrict__ tpt, const int32_t* __restrict__ spt,
+                                       const int32_t* __restrict__ cmp, int64_t npairs,
+                                       const double* __restrict__ px, const double* __restrict__ py,
+                                       const double* __restrict__ ph, double* __restrict__ val,
+                                       unsigned long long* __restrict__ nfallback) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  const int32_t a = tpt[i], b = spt[i];
+  const double dx = px[a] - px[b], dy = py[a] - py[b];
+  const double rho = sqrt(dx * dx + dy * dy);
+  const double zeta = ph[a] + ph[b];
+  const CompInfo c = comps[cmp[i]];
+  double v0;
+  if (surrogate_in_domain(dm, rho, zeta)) {
+    const int sc = smap[cmp[i]];
+    double lr[kTabK], lz[kTabK];
+    const int cell = table_cell(g, rho, zeta, lr, lz);
+    const double* blk = tab + ((int64_t)sc * g.npr * g.npz + cell) * nout * kTabK * kTabK;
+    v0 = learned_pair_value(c, lad + (int64_t)sc * kLadder, dm, rho, zeta, table_value(blk, 0, lr, lz));
+  } else {
+    Scatter sc;
+    local_coeffs(md, sc);
+    initial_values(md, sc, c, 1.0, rho, zeta, 0, &v0, nullptr);
+    atomicAdd(nfallback, 1ull);
+  }
+  val[i] = v0 * (1.0 / (4.0 * 3.14159265358979323846));
+}
+
+// The interpolation alone on given node values (tests): out[i][j] for nout outputs.
+__global__ void interp2d_kernel(TableGrid g, int nout, const double* __restrict__ nodes, int64_t n,
+                                const double* __restrict__ rho, const double* __restrict__ zeta,
+                                double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lr[kTabK], lz[kTabK];
+  const int cell = table_cell(g, rho[i], zeta[i], lr, lz);
+  const double* blk = nodes + (int64_t)cell * nout * kTabK * kTabK;
+  for (int j = 0; j < nout; ++j) out[i * nout + j] = table_value(blk, j, lr, lz);
 }
 
 __global__ void density_kernel(Medium md, CompInfo c, int64_t nk, const double* __restrict__ kre,
@@ -652,6 +838,14 @@ int upload_gl(hipStream_t st) {
   gl_nodes(kGL, x, w);
   FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(x)));
   FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(w)));
+  double cx[kTabK], cw[kTabK];
+  for (int k = 0; k < kTabK; ++k) {
+    const double th = M_PI * (2.0 * k + 1.0) / (2.0 * kTabK);
+    cx[k] = std::cos(th);
+    cw[k] = ((k & 1) ? -1.0 : 1.0) * std::sin(th);
+  }
+  FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_chx), cx, sizeof(cx)));
+  FMM_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_chw), cw, sizeof(cw)));
   done[dev] = true;
   return FMMLM_OK;
 }
@@ -865,6 +1059,117 @@ int gpu_surrogate_nearfield(const Medium& md, const std::vector<CompInfo>& comps
   hipFree(dy);
   hipFree(dfb);
   return rc;
+}
+
+// ---- table form (host side)
+int gpu_table_fill(const Medium& md, const std::vector<CompInfo>& comps, const double* d_lad,
+                   const SurrogateDomain& dm, const TableGrid& g, int nmax, double* d_tab, hipStream_t st) {
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  CompInfo* dc = nullptr;
+  FMM_HIP_TRY(hipMalloc(&dc, comps.size() * sizeof(CompInfo)));
+  FMM_HIP_TRY(hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st));
+  const int64_t n = (int64_t)comps.size() * g.npr * g.npz * kTabK * kTabK;
+  table_fill_kernel<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(md, dc, (int)comps.size(), d_lad, dm, g, nmax, d_tab);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(dc);
+  if (e != hipSuccess) {
+    set_last_error(std::string("table fill: ") + hipGetErrorString(e));
+    return FMMLM_EDEVICE;
+  }
+  return FMMLM_OK;
+}
+
+int gpu_table_tasks(const Medium& md, const std::vector<CompInfo>& comps, const std::vector<int32_t>& smap,
+                    const double* d_lad, const SurrogateDomain& dm, const TableGrid& g, const double* d_tab,
+                    int ynmax, const std::vector<SommTask>& tasks, int nmax, double* d_out, int64_t* n_used,
+                    hipStream_t st, int32_t* h_used) {
+  *n_used = 0;
+  if (tasks.empty()) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  const int nt = (int)tasks.size();
+  CompInfo* dc = nullptr;
+  SommTask* dt = nullptr;
+  int32_t *dmap = nullptr, *dused = nullptr;
+  hipError_t e = hipMalloc(&dc, comps.size() * sizeof(CompInfo));
+  if (e == hipSuccess) e = hipMalloc(&dt, tasks.size() * sizeof(SommTask));
+  if (e == hipSuccess) e = hipMalloc(&dmap, smap.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&dused, nt * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dt, tasks.data(), tasks.size() * sizeof(SommTask), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dmap, smap.data(), smap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  std::vector<int32_t> used(nt);
+  if (e == hipSuccess) {
+    table_task_kernel<<<(nt + 63) / 64, 64, 0, st>>>(md, dc, dmap, d_lad, dm, g, d_tab, ynmax, dt, nt, nmax, d_out,
+                                                     dused);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(used.data(), dused, nt * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(dc);
+  hipFree(dt);
+  hipFree(dmap);
+  hipFree(dused);
+  if (e != hipSuccess) {
+    set_last_error(std::string("table tasks: ") + hipGetErrorString(e));
+    return FMMLM_EDEVICE;
+  }
+  for (int32_t u : used) *n_used += u;
+  if (h_used) std::copy(used.begin(), used.end(), h_used);
+  return FMMLM_OK;
+}
+
+int gpu_table_nearfield(const Medium& md, const std::vector<CompInfo>& comps, const std::vector<int32_t>& smap,
+                        const double* d_lad, const SurrogateDomain& dm, const TableGrid& g, const double* d_tab,
+                        int nout, const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp, int64_t npairs,
+                        const double* px, const double* py, const double* ph, double* d_val, int64_t* n_fallback,
+                        hipStream_t st) {
+  *n_fallback = 0;
+  if (npairs == 0) return FMMLM_OK;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  CompInfo* dc = nullptr;
+  int32_t* dmap = nullptr;
+  unsigned long long* dfb = nullptr;
+  hipError_t e = hipMalloc(&dc, comps.size() * sizeof(CompInfo));
+  if (e == hipSuccess) e = hipMalloc(&dmap, smap.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&dfb, sizeof(unsigned long long));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dc, comps.data(), comps.size() * sizeof(CompInfo), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dmap, smap.data(), smap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(dfb, 0, sizeof(unsigned long long), st);
+  unsigned long long fb = 0;
+  if (e == hipSuccess) {
+    table_nearfield_kernel<<<(unsigned)((npairs + 255) / 256), 256, 0, st>>>(
+        md, dc, dmap, d_lad, dm, g, d_tab, nout, d_tpt, d_spt, d_comp, npairs, px, py, ph, d_val, dfb);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&fb, dfb, sizeof(fb), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(dc);
+  hipFree(dmap);
+  hipFree(dfb);
+  if (e != hipSuccess) {
+    set_last_error(std::string("table near field: ") + hipGetErrorString(e));
+    return FMMLM_EDEVICE;
+  }
+  *n_fallback = (int64_t)fb;
+  return FMMLM_OK;
+}
+
+int gpu_interp2d(const TableGrid& g, int nout, const double* d_nodes, int64_t n, const double* d_rho,
+                 const double* d_zeta, double* d_out, hipStream_t st) {
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  interp2d_kernel<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(g, nout, d_nodes, n, d_rho, d_zeta, d_out);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMMLM_OK;
 }
 
 }  // namespace fmmlm

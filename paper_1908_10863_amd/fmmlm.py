@@ -89,7 +89,9 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
            "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve",
            "fmm_layered_plan_general",
-           "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam", "fmm_layered_plan_lists"]
+           "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam", "fmm_layered_plan_lists",
+           "fmm_layered_tables_create", "fmm_layered_tables_create_for_plan", "fmm_layered_tables_info",
+           "fmm_layered_interp2d"]
 STAGES = ["gather", "p2m", "m2m", "m2l_top", "m2l", "m2l_reduce", "l2l", "l2p", "p2p_free", "p2p_reaction",
           "combine"]
 
@@ -167,6 +169,17 @@ def lib():
     L.fmm_layered_surrogate_eval.restype = ctypes.c_int
     L.fmm_layered_surrogate_samples.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp]
     L.fmm_layered_surrogate_samples.restype = ctypes.c_int
+    L.fmm_layered_tables_create.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_double, vp, ctypes.POINTER(vp)]
+    L.fmm_layered_tables_create.restype = ctypes.c_int
+    L.fmm_layered_tables_create_for_plan.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    L.fmm_layered_tables_create_for_plan.restype = ctypes.c_int
+    L.fmm_layered_tables_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    L.fmm_layered_tables_info.restype = ctypes.c_int
+    L.fmm_layered_interp2d.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.fmm_layered_interp2d.restype = ctypes.c_int
     L.fmm_layered_surrogate_forward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
     L.fmm_layered_surrogate_forward.restype = ctypes.c_int
     L.fmm_layered_surrogate_adam.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
@@ -373,11 +386,23 @@ def density_asymptotic(d, eps, lt, ls, a, b):
 
 
 class Surrogate:
-    """Learned form: fmm_layered_surrogate_* on a medium (or a plan's medium and domain)."""
+    """Learned form: fmm_layered_surrogate_* on a medium (or a plan's medium and domain).
+    tables=True builds the table form instead (fmm_layered_tables_create*), which a plan
+    takes the same way."""
 
-    def __init__(self, d=None, eps=None, p=None, rho_max=None, zeta_max=None, seed=1, plan=None):
+    def __init__(self, d=None, eps=None, p=None, rho_max=None, zeta_max=None, seed=1, plan=None,
+                 tables=False, stream=None):
         h = ctypes.c_void_p()
-        if plan is not None:
+        if tables:
+            if plan is not None:
+                check(lib().fmm_layered_tables_create_for_plan(plan._h, _stream_handle(stream), ctypes.byref(h)))
+                p = plan.p
+            else:
+                d = _host(d, np.float64)
+                eps = _host(eps, np.float64)
+                check(lib().fmm_layered_tables_create(len(d), _ptr(d), _ptr(eps), p, float(rho_max),
+                                                      float(zeta_max), _stream_handle(stream), ctypes.byref(h)))
+        elif plan is not None:
             check(lib().fmm_layered_surrogate_create_for_plan(plan._h, seed, ctypes.byref(h)))
             p = plan.p
         else:
@@ -387,6 +412,14 @@ class Surrogate:
                                                      float(zeta_max), seed, ctypes.byref(h)))
         self._h = h
         self.nout = 4 * p + 1
+
+    def table_info(self) -> dict:
+        """Table form: panels per direction, device bytes, creation seconds."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        nb, sec = ctypes.c_int64(), ctypes.c_double()
+        check(lib().fmm_layered_tables_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(nb),
+                                            ctypes.byref(sec)))
+        return {"npr": a.value, "npz": b.value, "bytes": nb.value, "seconds": sec.value}
 
     def train(self, nsamples=None, steps=None, batch=None, lr=None, seed=None, stream=None) -> dict:
         o = TrainOpts()
