@@ -361,6 +361,36 @@ int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, con
                            const double* rho, const double* z, int32_t nmax, double* out,
                            void* hip_stream);
 
+/*
+ * Allocation-free form of fmm_layered_sommerfeld, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes the same values with the same
+ * kernels, but rho, z and out are device arrays and the call allocates
+ * nothing: the component and one task per point are staged in a file-scope
+ * device array of FMMLM_NOALLOC_MAX_POINTS * 32 + 256 bytes (about 2 MiB),
+ * which each device the library runs on holds until the process ends.  Its
+ * device address is looked up (and the quadrature's node table written to
+ * constant memory) on the first call on each device; later calls only launch
+ * kernels on hip_stream and return without synchronising.
+ *
+ *  medium, lt, ls, a, b, S, nmax   as for fmm_layered_sommerfeld (host scalars and arrays)
+ *  npts           1..FMMLM_NOALLOC_MAX_POINTS
+ *  rho, z         device [npts]; a point with rho < 0, z <= 0 or a non-finite
+ *                 value gets NaN in all of its outputs
+ *  out            device [npts][(nmax+1)(nmax+2)/2], entry N(N+1)/2 + M
+ *
+ * Every call on a device shares that device's staging array: calls that
+ * overlap in time on one device (other streams, other host threads) race and
+ * must be ordered by the caller.  Errors: FMMLM_EINVAL (npts above the limit
+ * or below 1, bad component, S or nmax, null pointer), medium errors,
+ * FMMLM_EDEVICE.
+ */
+#define FMMLM_NOALLOC_MAX_POINTS 65536
+int fmm_layered_sommerfeld_noalloc(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                                   int32_t lt, int32_t ls, int32_t a, int32_t b, double S, int64_t npts,
+                                   const double* rho, const double* z, int32_t nmax, double* out,
+                                   void* hip_stream);
+
 /* ---- learned form: image ladder + MLP surrogate of the reaction Sommerfeld integrals
  *
  * Reaction component (lt, ls, a, b) of the medium, density sigma(k) with

@@ -1858,6 +1858,38 @@ int fmm_layered_sommerfeld(int32_t n_interfaces, const double* z_interfaces, con
   return rc;
 }
 
+int fmm_layered_sommerfeld_noalloc(int32_t n_interfaces, const double* z_interfaces, const double* eps,
+                                   int32_t lt, int32_t ls, int32_t a, int32_t b, double S, int64_t npts,
+                                   const double* rho, const double* z, int32_t nmax, double* out,
+                                   void* hip_stream) {
+  if (!rho || !z || !out || nmax < 0 || nmax > 2 * FMMLM_PMAX || !(S > 0.0) || !std::isfinite(S))
+    return FMMLM_EINVAL;
+  if (npts < 1 || npts > FMMLM_NOALLOC_MAX_POINTS) {
+    set_last_error("fmm_layered_sommerfeld_noalloc: npts must be 1.." +
+                   std::to_string(FMMLM_NOALLOC_MAX_POINTS));
+    return FMMLM_EINVAL;
+  }
+  // the medium is read from fixed-size host arrays (no vectors: nothing is allocated)
+  Medium md;
+  std::memset(&md, 0, sizeof(md));
+  if (n_interfaces < 0 || n_interfaces > kMaxL) return FMMLM_EINVAL;
+  if (n_interfaces > 0) {
+    if (!z_interfaces || !eps) return FMMLM_EINVAL;
+    const int L = n_interfaces;
+    for (int i = 0; i < L; ++i)
+      if (!std::isfinite(z_interfaces[i]) || (i > 0 && !(z_interfaces[i] < z_interfaces[i - 1])))
+        return FMMLM_EINTERFACES;
+    for (int i = 0; i <= L; ++i)
+      if (!std::isfinite(eps[i]) || !(eps[i] > 0.0)) return FMMLM_EEPS;
+    md = make_medium(L, z_interfaces, eps);
+    if (lt < 0 || lt > L || ls < 0 || ls > L || a < 1 || a > 2 || b < 1 || b > 2) return FMMLM_EINVAL;
+    if ((a == 1 && lt > L - 1) || (a == 2 && lt < 1) || (b == 1 && ls > L - 1) || (b == 2 && ls < 1))
+      return FMMLM_EINVAL;
+  }
+  const CompInfo c = make_comp(md, lt, ls, a, b);
+  return gpu_sommerfeld_noalloc(md, c, S, npts, rho, z, nmax, out, static_cast<hipStream_t>(hip_stream));
+}
+
 int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const double* eps, int32_t lt,
                         int32_t ls, int32_t a, int32_t b, int64_t nk, const double* k_re, const double* k_im,
                         double* out_re, double* out_im, void* hip_stream) {

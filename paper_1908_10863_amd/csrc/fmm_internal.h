@@ -274,6 +274,8 @@ struct CompInfo {
 int gpu_sommerfeld_tables(const Medium& md, const std::vector<CompInfo>& comps,
                           const std::vector<SommTask>& tasks, int nmax, double* d_out,
                           hipStream_t st);
+int gpu_sommerfeld_noalloc(const Medium& md, const CompInfo& c, double S, int64_t npts, const double* rho,
+                           const double* z, int nmax, double* out, hipStream_t st);
 int gpu_reaction_nearfield(const Medium& md, const std::vector<CompInfo>& comps,
                            const int32_t* d_tpt, const int32_t* d_spt, const int32_t* d_comp,
                            int64_t npairs, const double* px, const double* py, const double* ph,

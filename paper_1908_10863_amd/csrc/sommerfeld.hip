@@ -850,6 +850,60 @@ int upload_gl(hipStream_t st) {
   return FMMLM_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free form
+// fmm_layered_sommerfeld_noalloc stages its component and per-point tasks in
+// `scratch`, a file-scope device array (each device holds its own copy for the
+// life of the process), instead of buffers allocated per call.  Host code
+// never passes the array's name to a kernel or a copy: it asks the runtime for
+// the array's device address once per device (noalloc_scratch) and uses that.
+constexpr size_t kNoAllocCompBytes = 256;  // the CompInfo, padded to keep the tasks aligned
+constexpr size_t kNoAllocBytes = kNoAllocCompBytes + (size_t)FMMLM_NOALLOC_MAX_POINTS * sizeof(SommTask);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static_assert(sizeof(CompInfo) <= kNoAllocCompBytes, "component does not fit its scratch slot");
+
+// Device address of this device's scratch array (looked up once per device).
+int noalloc_scratch(unsigned char** out) {
+  static std::mutex mu;
+  static unsigned char* ptr[kMaxDevices] = {};
+  int dev = 0;
+  FMM_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FMMLM_EDEVICE;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    FMM_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return FMMLM_EDEVICE;
+    ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = ptr[dev];
+  return FMMLM_OK;
+}
+
+// Stages the component and one task per point.  A point with rho < 0, z <= 0
+// or a non-finite value gets a harmless task (rho = 0, z = 1, so the
+// quadrature stays bounded); noalloc_mark_kernel then writes NaN over its
+// outputs.
+__device__ inline bool noalloc_valid(double r, double zz) {
+  return (r >= 0.0) && (zz > 0.0) && isfinite(r) && isfinite(zz);
+}
+
+__global__ void noalloc_tasks_kernel(CompInfo c, double S, const double* __restrict__ rho,
+                                     const double* __restrict__ z, int64_t n, CompInfo* __restrict__ comp,
+                                     SommTask* __restrict__ tasks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *comp = c;
+  if (i >= n) return;
+  const double r = rho[i], zz = z[i];
+  tasks[i] = noalloc_valid(r, zz) ? SommTask{0, S, r, zz} : SommTask{0, S, 0.0, 1.0};
+}
+
+__global__ void noalloc_mark_kernel(const double* __restrict__ rho, const double* __restrict__ z, int64_t n,
+                                    int per, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || noalloc_valid(rho[i], z[i])) return;
+  for (int j = 0; j < per; ++j) out[i * per + j] = __builtin_nan("");
+}
+
 }  // namespace
 
 // Shortest ray path from the source's exit interface to the target's entry
@@ -1168,6 +1222,28 @@ int gpu_interp2d(const TableGrid& g, int nout, const double* d_nodes, int64_t n,
   int rc = upload_gl(st);
   if (rc) return rc;
   interp2d_kernel<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(g, nout, d_nodes, n, d_rho, d_zeta, d_out);
+  FMM_HIP_TRY(hipGetLastError());
+  return FMMLM_OK;
+}
+
+// S^N I_{N,M} for device arrays rho, z of npts points into out (device),
+// asynchronous on st, with no allocation: the per-call staging goes to this
+// device's scratch array.  npts <= FMMLM_NOALLOC_MAX_POINTS (checked by the caller).
+int gpu_sommerfeld_noalloc(const Medium& md, const CompInfo& c, double S, int64_t npts, const double* rho,
+                           const double* z, int nmax, double* out, hipStream_t st) {
+  if (npts < 1 || npts > FMMLM_NOALLOC_MAX_POINTS) return FMMLM_EINVAL;
+  int rc = upload_gl(st);
+  if (rc) return rc;
+  unsigned char* base = nullptr;
+  if ((rc = noalloc_scratch(&base))) return rc;
+  CompInfo* dcomp = reinterpret_cast<CompInfo*>(base);
+  SommTask* dtask = reinterpret_cast<SommTask*>(base + kNoAllocCompBytes);
+  const unsigned nb = (unsigned)((npts + 63) / 64);
+  noalloc_tasks_kernel<<<nb, 64, 0, st>>>(c, S, rho, z, npts, dcomp, dtask);
+  FMM_HIP_TRY(hipGetLastError());
+  sommerfeld_table_kernel<<<nb, 64, 0, st>>>(md, dcomp, dtask, (int)npts, nmax, out);
+  FMM_HIP_TRY(hipGetLastError());
+  noalloc_mark_kernel<<<nb, 64, 0, st>>>(rho, z, npts, ncoef(nmax), out);
   FMM_HIP_TRY(hipGetLastError());
   return FMMLM_OK;
 }

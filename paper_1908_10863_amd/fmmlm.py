@@ -88,7 +88,7 @@ EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_la
            "fmm_layered_surrogate_destroy", "fmm_layered_surrogate_params",
            "fmm_layered_surrogate_grad", "fmm_layered_surrogate_eval",
            "fmm_layered_surrogate_samples", "fmm_layered_plan_set_variants", "fmm_layered_solve",
-           "fmm_layered_plan_general",
+           "fmm_layered_plan_general", "fmm_layered_sommerfeld_noalloc",
            "fmm_layered_surrogate_forward", "fmm_layered_surrogate_adam", "fmm_layered_plan_lists",
            "fmm_layered_tables_create", "fmm_layered_tables_create_for_plan", "fmm_layered_tables_info",
            "fmm_layered_interp2d"]
@@ -140,6 +140,8 @@ def lib():
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp]
     L.fmm_layered_sommerfeld.restype = ctypes.c_int
+    L.fmm_layered_sommerfeld_noalloc.argtypes = L.fmm_layered_sommerfeld.argtypes
+    L.fmm_layered_sommerfeld_noalloc.restype = ctypes.c_int
     L.fmm_layered_density.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp, vp,
                                       vp, vp]
@@ -357,6 +359,33 @@ def sommerfeld(d, eps, lt, ls, a, b, S, rho, z, nmax, stream=None):
     out = np.zeros((len(rho), nc))
     check(lib().fmm_layered_sommerfeld(len(d), _ptr(d), _ptr(eps), lt, ls, a, b, float(S), len(rho),
                                        _ptr(rho), _ptr(z), nmax, _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def sommerfeld_noalloc(d, eps, lt, ls, a, b, S, rho, z, nmax, out, stream=None):
+    """fmm_layered_sommerfeld_noalloc: rho, z (CUDA float64 [npts]) -> out (CUDA float64
+    [npts, (nmax+1)(nmax+2)/2]), asynchronous on the stream, allocating nothing."""
+    import torch
+    for name, t in (("rho", rho), ("z", z), ("out", out)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
+    d = _host(d, np.float64)
+    eps = _host(eps, np.float64) if len(d) else np.ones(1)
+    check(lib().fmm_layered_sommerfeld_noalloc(len(d), _ptr(d), _ptr(eps), lt, ls, a, b, float(S), rho.numel(),
+                                               ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                               nmax, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def interp2d(npr, npz, rho_max, zeta_max, nodes, rho, zeta, stream=None):
+    """The table form's interpolation on given node values [npr * npz, nout, 144]."""
+    nodes = _host(nodes, np.float64)
+    nout = nodes.shape[1]
+    rho = _host(np.atleast_1d(rho), np.float64)
+    zeta = _host(np.atleast_1d(zeta), np.float64)
+    out = np.zeros((len(rho), nout))
+    check(lib().fmm_layered_interp2d(npr, npz, float(rho_max), float(zeta_max), nout, _ptr(nodes), len(rho),
+                                     _ptr(rho), _ptr(zeta), _ptr(out), _stream_handle(stream)))
     return out
 
 
