@@ -222,7 +222,10 @@ def potential(d, eps, x, y, z, layer, q, targets=None, method="auto", parts=3) -
     """Direct sum of eq. totalinteraction at the selected targets.
 
     parts: 1 free space (j != i, same layer), 2 reaction (all j incl. j == i), 3 both.
-    method: 'quad' (any L), 'image3' (three layers), 'auto' (image3 when L == 2)."""
+    method: 'quad' (any L), 'image3' (three layers), 'table' (any L: the quadrature's kernel
+    tabulated per component and interpolated, certified against the quadrature at random
+    points to 1e-12 of the component's largest value; for sums too large for 'quad'),
+    'auto' (image3 when L == 2)."""
     d = _f64(d)
     eps = _f64(eps)
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
@@ -233,13 +236,15 @@ def potential(d, eps, x, y, z, layer, q, targets=None, method="auto", parts=3) -
     targets = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
     if method == "auto":
         method = "image3" if len(d) == 2 else "quad"
-    m = {"quad": 0, "image3": 1}[method]
+    m = {"quad": 0, "image3": 1, "table": 2}[method]
     out = np.zeros(len(targets))
     rc = _load().oracle_potential(len(d), _dp(d), _dp(eps), n, _dp(x), _dp(y), _dp(z),
                                   layer.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(q),
                                   len(targets),
                                   targets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   m, int(parts), _dp(out))
+    if rc == -5:
+        raise ValueError("oracle_potential: the tabulated kernels could not be certified for this geometry")
     if rc:
         raise ValueError(f"oracle_potential failed ({rc})")
     return out

@@ -369,9 +369,193 @@ static double zeta_of(const double* d, int lt, int ls, int a, int b, double z,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tabulated reaction kernels (method 2), for direct sums too large for the  */
+/* per-pair quadrature.  For every component the kernel                      */
+/*   K(rho, zeta) = 1/(4pi) int J0(k rho) e^{-k zeta} sigma(k) dk            */
+/* is computed by the shared rule at the nodes of a tensor grid over the     */
+/* pairs' (rho, zeta) box and interpolated by polynomials of degree KT_DEG   */
+/* in each variable (barycentric formula, Chebyshev-Lobatto points).  rho    */
+/* panels have width at most zeta_min (K's singularities lie at least        */
+/* zeta_min off the real rho axis); zeta panels double in width from         */
+/* zeta_min, as their distance to the singularity at zeta = 0 does.  Before  */
+/* use, the interpolant is certified at KT_CHECK random points per component */
+/* against the shared rule applied directly: the largest deviation must stay */
+/* below KT_TOL times the component's largest node value, else the call      */
+/* fails (returns -5).                                                       */
+/* ------------------------------------------------------------------------ */
+#define KT_DEG 24
+#define KT_NP (KT_DEG + 1)
+#define KT_CHECK 48
+#define KT_TOL 1e-12
+#define KT_MAXPAN 256
+
+typedef struct {
+  int npr, npz;
+  double hr, zmin, zmax;
+  double xk[KT_NP], wk[KT_NP]; /* nodes cos(j pi / KT_DEG) and barycentric weights */
+  double* val;                 /* [comp][npr * KT_NP][npz * KT_NP] (NULL for invalid components) */
+  double* cmax;                /* [comp] largest |node value| */
+} ktab_t;
+
+static double kt_zlo(const ktab_t* T, int pz) { return T->zmin * ldexp(1.0, pz); }
+static double kt_zhi(const ktab_t* T, int pz) {
+  const double h = T->zmin * ldexp(1.0, pz + 1);
+  return (pz == T->npz - 1 || h > T->zmax) ? T->zmax : h;
+}
+
+/* barycentric basis at local coordinate u in [-1, 1] */
+static void kt_basis(const ktab_t* T, double u, double* l) {
+  double s = 0.0;
+  for (int j = 0; j < KT_NP; ++j) {
+    const double du = u - T->xk[j];
+    if (du == 0.0) {
+      for (int i = 0; i < KT_NP; ++i) l[i] = (i == j) ? 1.0 : 0.0;
+      return;
+    }
+    l[j] = T->wk[j] / du;
+    s += l[j];
+  }
+  for (int j = 0; j < KT_NP; ++j) l[j] /= s;
+}
+
+static void kt_locate(const ktab_t* T, double rho, double zeta, int* pr, int* pz, double* lr, double* lz) {
+  int a = (int)(rho / T->hr);
+  if (a < 0) a = 0;
+  if (a > T->npr - 1) a = T->npr - 1;
+  int b = (int)floor(log2(zeta / T->zmin));
+  if (b < 0) b = 0;
+  if (b > T->npz - 1) b = T->npz - 1;
+  kt_basis(T, 2.0 * (rho - a * T->hr) / T->hr - 1.0, lr);
+  const double lo = kt_zlo(T, b), hi = kt_zhi(T, b);
+  kt_basis(T, 2.0 * (zeta - lo) / (hi - lo) - 1.0, lz);
+  *pr = a;
+  *pz = b;
+}
+
+static double kt_eval(const ktab_t* T, int c, int pr, int pz, const double* lr, const double* lz) {
+  const int nz = T->npz * KT_NP;
+  const double* v = T->val + (size_t)c * (size_t)(T->npr * KT_NP) * nz;
+  double acc = 0.0;
+  for (int a = 0; a < KT_NP; ++a) {
+    const double* row = v + (size_t)(pr * KT_NP + a) * nz + pz * KT_NP;
+    double r = 0.0;
+    for (int b = 0; b < KT_NP; ++b) r += lz[b] * row[b];
+    acc += lr[a] * r;
+  }
+  return acc;
+}
+
+/* the shared rule applied to one (rho, zeta) of component c */
+static double kt_direct(const rule_t* rule, const double* sg, double rho, double zeta) {
+  double acc = 0.0, cmp = 0.0;
+  for (int kk = 0; kk < rule->nn; ++kk) {
+    const double f = rule->w[kk] * j0(rule->k[kk] * rho) * exp(-rule->k[kk] * zeta) * sg[kk];
+    const double t = acc + f;
+    if (fabs(acc) >= fabs(f)) cmp += (acc - t) + f; else cmp += (f - t) + acc;
+    acc = t;
+  }
+  return (acc + cmp) / (4.0 * OR_PI);
+}
+
+/* valid[c] marks the components to tabulate; sig [comp][nn] from the rule */
+static int kt_build(ktab_t* T, const rule_t* rule, const double* sig, const int* valid, int ncomp,
+                    double rho_max, double zmin, double zmax) {
+  T->val = NULL;
+  T->cmax = NULL;
+  if (!(zmin > 0.0) || !(zmax >= zmin)) return -5;
+  T->npr = (int)ceil(rho_max / zmin);
+  if (T->npr < 1) T->npr = 1;
+  if (T->npr > KT_MAXPAN) return -5; /* pairs too close to an interface for a table: use quadrature */
+  T->hr = (rho_max > 0.0 ? rho_max : zmin) / T->npr;
+  T->zmin = zmin;
+  T->zmax = zmax;
+  T->npz = 1;
+  while (T->zmin * ldexp(1.0, T->npz) < zmax) ++T->npz;
+  for (int j = 0; j < KT_NP; ++j) {
+    T->xk[j] = cos(OR_PI * j / KT_DEG);
+    T->wk[j] = ((j & 1) ? -1.0 : 1.0) * ((j == 0 || j == KT_DEG) ? 0.5 : 1.0);
+  }
+  const int nr = T->npr * KT_NP, nz = T->npz * KT_NP, nn = rule->nn;
+  double* rn = (double*)malloc(sizeof(double) * nr);
+  double* zn = (double*)malloc(sizeof(double) * nz);
+  double* J = (double*)malloc(sizeof(double) * (size_t)nr * nn);
+  double* E = (double*)malloc(sizeof(double) * (size_t)nz * nn);
+  T->val = (double*)calloc((size_t)ncomp * nr * nz, sizeof(double));
+  T->cmax = (double*)calloc(ncomp, sizeof(double));
+  if (!rn || !zn || !J || !E || !T->val || !T->cmax) {
+    free(rn); free(zn); free(J); free(E);
+    return -3;
+  }
+  for (int a = 0; a < T->npr; ++a)
+    for (int j = 0; j < KT_NP; ++j) rn[a * KT_NP + j] = (a + 0.5 + 0.5 * T->xk[j]) * T->hr;
+  for (int b = 0; b < T->npz; ++b) {
+    const double lo = kt_zlo(T, b), hi = kt_zhi(T, b);
+    for (int j = 0; j < KT_NP; ++j) zn[b * KT_NP + j] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * T->xk[j];
+  }
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < nr; ++i)
+    for (int kk = 0; kk < nn; ++kk) J[(size_t)i * nn + kk] = rule->w[kk] * j0(rule->k[kk] * rn[i]);
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < nz; ++i)
+    for (int kk = 0; kk < nn; ++kk) E[(size_t)i * nn + kk] = exp(-rule->k[kk] * zn[i]);
+  /* node values: K[c][i][j] = sum_k J[i][k] sigma_c[k] E[j][k] / (4 pi) */
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+  for (int c = 0; c < ncomp; ++c)
+    for (int i = 0; i < nr; ++i) {
+      if (!valid[c]) continue;
+      const double* sg = sig + (size_t)c * nn;
+      const double* Ji = J + (size_t)i * nn;
+      double* out = T->val + ((size_t)c * nr + i) * nz;
+      for (int j = 0; j < nz; ++j) {
+        const double* Ej = E + (size_t)j * nn;
+        double acc = 0.0;
+        for (int kk = 0; kk < nn; ++kk) acc += Ji[kk] * sg[kk] * Ej[kk];
+        out[j] = acc / (4.0 * OR_PI);
+      }
+    }
+  free(rn); free(zn); free(J); free(E);
+  for (int c = 0; c < ncomp; ++c) {
+    if (!valid[c]) continue;
+    const double* v = T->val + (size_t)c * nr * nz;
+    for (size_t i = 0; i < (size_t)nr * nz; ++i)
+      if (fabs(v[i]) > T->cmax[c]) T->cmax[c] = fabs(v[i]);
+  }
+  /* certification at seeded random points (a 64-bit linear congruential stream) */
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int c = 0; c < ncomp; ++c) {
+    if (!valid[c]) continue;
+    uint64_t st = 0x9E3779B97F4A7C15ull ^ (uint64_t)(c + 1);
+    for (int t = 0; t < KT_CHECK; ++t) {
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      const double u1 = (double)(st >> 11) * 0x1.0p-53;
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      const double u2 = (double)(st >> 11) * 0x1.0p-53;
+      const double rho = u1 * T->npr * T->hr, zeta = zmin + u2 * (zmax - zmin);
+      int pr, pz;
+      double lr[KT_NP], lz[KT_NP];
+      kt_locate(T, rho, zeta, &pr, &pz, lr, lz);
+      const double got = kt_eval(T, c, pr, pz, lr, lz);
+      const double ref = kt_direct(rule, sig + (size_t)c * nn, rho, zeta);
+      if (!(fabs(got - ref) <= KT_TOL * T->cmax[c])) {
+#pragma omp atomic write
+        bad = 1;
+      }
+    }
+  }
+  return bad ? -5 : 0;
+}
+
+static void kt_free(ktab_t* T) {
+  free(T->val);
+  free(T->cmax);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Direct potential at selected targets.                                     */
 /*   method 0: reaction kernels by quadrature (any number of layers)         */
 /*   method 1: reaction kernels by the three-layer image series (L == 2)     */
+/*   method 2: reaction kernels from certified tables (any number of layers) */
 /*   parts   : bit 0 free space, bit 1 reaction                              */
 /* Targets are indices into the N points; phi_out has nt entries.            */
 /* ------------------------------------------------------------------------ */
@@ -390,7 +574,10 @@ static int potential_impl(int L, const double* d, const double* acoef, const dou
   /* quadrature set-up: shared rule, sigma tabulated per component at nodes */
   rule_t rule = {0, NULL, NULL};
   double* sig = NULL;
-  if ((parts & 2) && method == 0) {
+  ktab_t ktab;
+  memset(&ktab, 0, sizeof(ktab));
+  double zeta_hi = 0.0, rho_span = 0.0;
+  if ((parts & 2) && (method == 0 || method == 2)) {
     double rho_max = 0.0, zeta_min = INFINITY;
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
     for (int64_t j = 0; j < n; ++j) {
@@ -401,8 +588,12 @@ static int potential_impl(int L, const double* d, const double* acoef, const dou
       const int l = layer[j];
       if (l <= L - 1 && z[j] - d[l] < zeta_min) zeta_min = z[j] - d[l];
       if (l >= 1 && d[l - 1] - z[j] < zeta_min) zeta_min = d[l - 1] - z[j];
+      if (l <= L - 1 && z[j] - d[l] > zeta_hi) zeta_hi = z[j] - d[l];
+      if (l >= 1 && d[l - 1] - z[j] > zeta_hi) zeta_hi = d[l - 1] - z[j];
     }
     rho_max = hypot(xmax - xmin, ymax - ymin);
+    rho_span = rho_max;
+    zeta_hi *= 2.0;
     zeta_min *= 2.0; /* every exponent is a target part plus a source part */
     if (make_rule(rho_max, zeta_min, min_thickness(L, d), &rule)) return -3;
     sig = (double*)malloc(sizeof(double) * (size_t)ncomp * rule.nn);
@@ -415,6 +606,23 @@ static int potential_impl(int L, const double* d, const double* acoef, const dou
           for (int c = 0; c < 4; ++c)
             sig[(size_t)((lt * (L + 1) + ls) * 4 + c) * rule.nn + i] = s4[c];
         }
+    if (method == 2) {
+      int* valid = (int*)calloc(ncomp, sizeof(int));
+      if (!valid) return -3;
+      for (int lt = 0; lt <= L; ++lt)
+        for (int ls = 0; ls <= L; ++ls)
+          for (int a = 1; a <= 2; ++a)
+            for (int b = 1; b <= 2; ++b)
+              valid[(lt * (L + 1) + ls) * 4 + 2 * (a - 1) + (b - 1)] = valid_side(L, lt, a) && valid_side(L, ls, b);
+      const int rc = kt_build(&ktab, &rule, sig, valid, ncomp, rho_span, zeta_min, zeta_hi);
+      free(valid);
+      if (rc) {
+        kt_free(&ktab);
+        free(sig);
+        free_rule(&rule);
+        return rc;
+      }
+    }
   }
   /* image-series coefficients per component */
   double* icoef = NULL;
@@ -488,6 +696,17 @@ static int potential_impl(int L, const double* d, const double* acoef, const dou
                 acc += jb[kk] * exp(-rule.k[kk] * zeta) * sg[kk];
               v += acc / (4.0 * OR_PI);
             }
+        } else if (method == 2) {
+          for (int a = 1; a <= 2; ++a)
+            for (int b = 1; b <= 2; ++b) {
+              if (!valid_side(L, li, a) || !valid_side(L, lj, b)) continue;
+              const double zeta = zeta_of(d, li, lj, a, b, zi, z[j]);
+              const int c = (li * (L + 1) + lj) * 4 + 2 * (a - 1) + (b - 1);
+              int pr, pz;
+              double lr[KT_NP], lz[KT_NP];
+              kt_locate(&ktab, rho, zeta, &pr, &pz, lr, lz);
+              v += kt_eval(&ktab, c, pr, pz, lr, lz);
+            }
         } else {
           for (int a = 1; a <= 2; ++a)
             for (int b = 1; b <= 2; ++b) {
@@ -512,6 +731,7 @@ static int potential_impl(int L, const double* d, const double* acoef, const dou
     phi_out[ti] = (fs + fc) + (rs + rc);
   }
   free(jbuf_all);
+  kt_free(&ktab);
   free(sig);
   free_rule(&rule);
   free(icoef);

@@ -380,3 +380,35 @@ def test_morton_sort_is_stable(oracle_mod):
     sk, perm = oracle_mod.morton_sort(keys)
     assert list(sk) == [1, 3, 3, 5, 5, 5]
     assert list(perm) == [3, 1, 4, 0, 2, 5]
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 1200), (3, 2000), (4, 2400)])
+def test_table_method_matches_quadrature(oracle_mod, cfg, n):
+    """The certified-table reaction kernels (method 'table', for sums too large for the
+    per-pair quadrature) against the per-pair quadrature on three, four and six-layer
+    workloads, and against the three-layer image series (no quadrature at all)."""
+    from paper_1908_10863_amd import workloads as W
+    w = W.config(cfg, n=n)
+    t = np.arange(0, n, 53)
+    args = (w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    tab = oracle_mod.potential(*args, targets=t, method="table", parts=2)
+    quad = oracle_mod.potential(*args, targets=t, method="quad", parts=2)
+    assert np.max(np.abs(tab - quad)) <= 1e-12 * np.max(np.abs(quad))
+    if cfg == 0:
+        img = oracle_mod.potential(*args, targets=t, method="image3", parts=2)
+        assert np.max(np.abs(tab - img)) <= 1e-12 * np.max(np.abs(img))
+    # the free part does not depend on the method
+    f = oracle_mod.potential(*args, targets=t, method="table", parts=1)
+    assert np.array_equal(f, oracle_mod.potential(*args, targets=t, method="quad", parts=1))
+
+
+def test_table_method_refuses_pairs_hugging_an_interface(oracle_mod):
+    """Points within 1e-4 of an interface would need thousands of rho panels: the table
+    method refuses (raises) instead of answering uncertified."""
+    rng = np.random.default_rng(4)
+    n = 60
+    lay = np.where(np.arange(n) < 30, 0, 1).astype(np.int32)
+    z = np.where(lay == 0, rng.uniform(5e-5, 0.3, n), -rng.uniform(5e-5, 0.3, n))
+    x, y = rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n)
+    with pytest.raises(ValueError, match="certified"):
+        oracle_mod.potential([0.0, -1.0], [1.0, 5.0, 2.0], x, y, z, lay, rng.uniform(-1, 1, n), method="table")
