@@ -28,6 +28,7 @@ METRIC = "FMM matvecs/sec at N=1M 3-layer p=10 vs plain FP64 GPU FMM at <=1e-5 r
 TRAFFIC_FILES = {
     "m2l": os.path.join(ROOT, "profiles", "m2l_mfma32_3layer_N1048576_p10_traffic.md"),
     "p2p_free": os.path.join(ROOT, "profiles", "p2p_leaf_3layer_N1048576_p10_traffic.md"),
+    "m2l_batch": os.path.join(ROOT, "profiles", "m2l_batch32_4layer_N524288_p10_rhs64_traffic.md"),
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_10863_amd", "csrc", "fmm.hip")
 # kernel that carries each stage of the FP32 form (one launch per evaluation)
@@ -100,12 +101,56 @@ def calibration_copy(dev):
     del a, b
 
 
-def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1):
+def root_side(w):
+    """The plan's common root box side: the larger of the xy extent and the largest height
+    of a point above or below its layer's interfaces, times 1 + 2^-20."""
+    import numpy as np
+    d, L, z, lay = np.asarray(w["d"]), len(w["d"]), w["z"], w["layer"]
+    m1, m2 = lay <= L - 1, lay >= 1
+    h = max((z[m1] - d[lay[m1]]).max(initial=0.0), (d[lay[m2] - 1] - z[m2]).max(initial=0.0))
+    return max(np.ptp(w["x"]), np.ptp(w["y"]), h) * (1 + 2.0 ** -20)
+
+
+def initial_value_forms(fmmlm, w, p):
+    """The table form and the trained network for workload w's medium over its plans'
+    (rho, zeta) box, with their creation times (tables: ladder fit and quadrature at the
+    nodes; network: ladder fit, 2M quadrature samples and 6000 Adam steps)."""
+    import math
+    wr = root_side(w) * (1 + 1e-9)
+    rmax, zmax = math.sqrt(2) * wr, 2 * wr
+    t0 = time.perf_counter()
+    tab = fmmlm.Surrogate(w["d"], w["eps"], p=p, rho_max=rmax, zeta_max=zmax, tables=True)
+    t_tab = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net = fmmlm.Surrogate(w["d"], w["eps"], p=p, rho_max=rmax, zeta_max=zmax, seed=11)
+    rep = net.train()
+    t_net = time.perf_counter() - t0
+    return tab, t_tab, net, t_net, rep
+
+
+def plan_times(fmmlm, w, p, cap, mac, precision, forms):
+    """Plan seconds (and the near-field and initial-value phases) with each source of the
+    Sommerfeld initial values: quadrature (None), tables, network."""
+    out = {}
+    for tag, sur in forms:
+        plan = fmmlm.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p, leaf_cap=cap,
+                          precision=precision, mac_d2=mac, surrogate=sur)
+        st = plan.stats()
+        plan.close()
+        out[tag] = {"plan_seconds": st["plan_seconds"], "initial_values_seconds": st["table_seconds"],
+                    "nearfield_seconds": st["nearfield_seconds"], "nearfield_pairs": st["p2p_reaction_pairs"],
+                    "tasks": st["n_sommerfeld_tasks"], "check": st["surrogate_check"]}
+    return out
+
+
+def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1, surrogate=None):
     """Plan one form, time `steps` evaluations (HIP events per stage), return stats.
     With rhs > 1 each step evaluates `rhs` charge vectors together (batched form)."""
     import torch
     plan = fmmlm.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p, leaf_cap=cap,
-                      precision=precision, mac_d2=mac, max_rhs=rhs)
+                      precision=precision, mac_d2=mac, max_rhs=rhs, surrogate=surrogate)
+    if rhs > 1:
+        plan.set_variants(batch_min=2)
     st = plan.stats()
     tag = "fp32" if precision else "fp64"
     print(f"[bench] {tag}: plan {st['plan_seconds']:.2f}s boxes={st['n_boxes']} "
@@ -138,7 +183,84 @@ def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1):
     print(f"[bench] {tag}: {rhs * steps / elapsed:.2f} matvec/s, stages(ms) " +
           ", ".join(f"{k}={v:.3f}" for k, v in avg.items()), file=sys.stderr, flush=True)
     return {"value": rhs * steps / elapsed, "ms": 1e3 * elapsed / steps, "stages": avg, "stats": st,
-            "phi": phi if rhs == 1 else phi[0], "phi_free": phi_free, "phi_reac": phi_reac}
+            "phi": phi if rhs == 1 else phi[0], "phi_free": phi_free, "phi_reac": phi_reac,
+            "phi_all": phi}
+
+
+def run_forms(fmmlm, workloads, oracle, dev, steps, warmup, metric_w, p):
+    """The other two forms on their own workloads, and the initial-value sources compared
+    (one JSON object): the batched form on the four-layer workload (64 charge vectors per
+    pass), the learned form on the six-region workload, plan times with quadrature, tables
+    and the network on the metric workload and the six-region one."""
+    import numpy as np
+    res = {}
+    # initial values on the metric workload: quadrature vs tables vs network (plan time only)
+    tab, t_tab, net, t_net, rep = initial_value_forms(fmmlm, metric_w, p)
+    res["initial_values_3layer"] = {
+        "workload": metric_w["name"], "tables_create_seconds": t_tab, "network_create_seconds": t_net,
+        "plans": plan_times(fmmlm, metric_w, p, 192, 4, fmmlm.FMMLM_FP32_COMPENSATED,
+                            [("quadrature", None), ("tables", tab), ("network", net)])}
+    tab.close()
+    net.close()
+    print(f"[bench] initial values, 3 layers: {res['initial_values_3layer']}", file=sys.stderr, flush=True)
+    # batched form: four layers, N = 524288, 64 charge vectors a pass (the table form
+    # supplies the plan's initial values and near-field kernels)
+    import math
+    w4 = workloads.config(3)
+    wr = root_side(w4) * (1 + 1e-9)
+    t0 = time.perf_counter()
+    tab4 = fmmlm.Surrogate(w4["d"], w4["eps"], p=10, rho_max=math.sqrt(2) * wr, zeta_max=2 * wr, tables=True)
+    t_tab4 = time.perf_counter() - t0
+    b = run_form(fmmlm, w4, 10, 128, 4, fmmlm.FMMLM_FP32_COMPENSATED, max(2, steps // 4), 1, dev, rhs=64,
+                 surrogate=tab4)
+    tab4.close()
+    rng = np.random.default_rng(77)
+    n4 = len(w4["x"])
+    t4 = np.sort(rng.choice(n4, 16, replace=False))
+    errs = []
+    for r in (0, 31, 63):
+        ref = oracle.potential(w4["d"], w4["eps"], w4["x"], w4["y"], w4["z"], w4["layer"], w4["q"][r],
+                               targets=t4, method="table")
+        errs.append(float(np.linalg.norm(b["phi_all"][r][t4] - ref) / np.linalg.norm(ref)))
+    bst = b["stats"]
+    dom = "m2l"
+    roof = stage_roofline(bst, 10, dom, b["stages"][dom], True, 64)
+    roof["kernel"] = "m2l_batch32_kernel"
+    roof["traffic"] = measured_traffic("m2l_batch")
+    res["batched"] = {"workload": w4["name"], "rhs": 64, "value": b["value"], "unit": "matvec/s",
+                      "ms_per_pass": b["ms"], "leaf_cap": 128, "mac_d2": 4,
+                      "rel_error_vs_oracle": {"vectors": [0, 31, 63], "targets": 16, "errors": errs},
+                      "plan_seconds": bst["plan_seconds"], "tables_create_seconds": t_tab4,
+                      "stage_ms": b["stages"], "roofline": roof,
+                      "batch_variant": bst["batch_variant"]}
+    print(f"[bench] batched: {res['batched']['value']:.1f} matvec/s, errors {errs}", file=sys.stderr, flush=True)
+    # learned form: six regions, N = 2097152, the network serving every initial value
+    w5 = workloads.config(4)
+    tab5, t_tab5, net5, t_net5, rep5 = initial_value_forms(fmmlm, w5, 10)
+    n5 = len(w5["x"])
+    t5 = np.sort(np.random.default_rng(5).choice(n5, 32, replace=False))
+    ref5 = oracle.potential(w5["d"], w5["eps"], w5["x"], w5["y"], w5["z"], w5["layer"], w5["q"][0], targets=t5,
+                            method="table")
+    learned = {}
+    for tag, prec in (("fp32", fmmlm.FMMLM_FP32_COMPENSATED), ("fp64", fmmlm.FMMLM_FP64)):
+        f = run_form(fmmlm, w5, 10, 192, 4, prec, max(2, steps // 2), 1, dev, surrogate=net5)
+        learned[tag] = {"value": f["value"], "ms_per_step": f["ms"],
+                        "rel_error_vs_oracle": float(np.linalg.norm(f["phi"][t5] - ref5) / np.linalg.norm(ref5)),
+                        "surrogate_check": f["stats"]["surrogate_check"],
+                        "surrogate_tasks": f["stats"]["surrogate_tasks"],
+                        "tasks": f["stats"]["n_sommerfeld_tasks"]}
+    res["learned"] = {"workload": w5["name"], "unit": "matvec/s", "leaf_cap": 192, "mac_d2": 4,
+                      "oracle_targets": 32, "forms": learned,
+                      "training": {"sample_seconds": rep5["sample_seconds"], "train_seconds": rep5["train_seconds"],
+                                   "loss_first": rep5["loss_first"], "loss_last": rep5["loss_last"],
+                                   "val_rms": rep5["val_rms"], "n_params": rep5["n_params"]},
+                      "tables_create_seconds": t_tab5, "network_create_seconds": t_net5,
+                      "plans": plan_times(fmmlm, w5, 10, 192, 4, fmmlm.FMMLM_FP32_COMPENSATED,
+                                          [("quadrature", None), ("tables", tab5), ("network", net5)])}
+    tab5.close()
+    net5.close()
+    print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
+    return res
 
 
 def stage_roofline(st, p, stage, ms, fp32, rhs=1):
@@ -226,6 +348,9 @@ def main():
                          "with quadrature)")
     ap.add_argument("--solve-n", type=int, default=1048576,
                     help="panels of the capacitance-style GMRES solve (0: skip it)")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="1: also run the batched form (four layers, 64 vectors) and the learned form "
+                         "(six regions, N = 2M) and compare the initial-value sources (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
@@ -249,6 +374,8 @@ def main():
                     args.warmup, dev, rhs=args.rhs)
     solve = (run_solve(fmmlm, workloads, dev, args.solve_n, restart=100, tol=1e-5, reps=3)
              if args.solve_n > 0 else None)
+    import oracle
+    forms = run_forms(fmmlm, workloads, oracle, dev, args.steps, args.warmup, w, p) if args.forms else None
     st = form["stats"]
     avg = form["stages"]
     dom = max((k for k in avg if stage_flops(st, p, k) > 0), key=lambda k: avg[k])
@@ -341,6 +468,7 @@ def main():
         # the plan's autotuner: main M2L shape (launch alone, then whole evaluations)
         # and the near-field split, each in ms
         "solve": solve,
+        "forms": forms,
         "tuning": {"m2l_variant": st["m2l_variant"],
                    "m2l_variant_ms": [round(x, 4) for x in st["m2l_variant_ms"]],
                    "m2l_eval_ms": [round(x, 4) for x in st["m2l_eval_ms"]],

@@ -284,3 +284,53 @@ def test_gain_over_quadrature(trained, F, W):
         _say(f"  {tag}: plan {st['plan_seconds']:.3f}s tables {st['table_seconds']:.3f}s "
              f"near field {st['nearfield_seconds']:.3f}s pairs {st['p2p_reaction_pairs']}")
     assert res["surrogate"]["nearfield_seconds"] < 0.5 * res["quadrature"]["nearfield_seconds"]
+
+
+def test_learned_form_full_size_six_regions(dev, F, W, oracle_mod):
+    """Workload 5 at its stated size: six regions, N = 2,097,152, p = 10.  The network is
+    created over the full plan's (rho, zeta) box, trained on 2M quadrature samples by its
+    own kernels, and serves every Sommerfeld initial value of the plan; the FMM (FP32 and
+    FP64 forms) is checked against the direct-sum oracle (certified tabulated kernels) at
+    32 seeded targets, <= 1e-5.  Matvecs per second and plan times are printed."""
+    import torch
+    _say("learned form, full size")
+    w = W.config(4)
+    n = len(w["x"])
+    assert n == 2097152 and len(w["eps"]) == 6
+    d, L, z, lay = np.asarray(w["d"]), len(w["d"]), w["z"], w["layer"]
+    m1, m2 = lay <= L - 1, lay >= 1
+    h = max((z[m1] - d[lay[m1]]).max(), (d[lay[m2] - 1] - z[m2]).max())
+    Wr = max(np.ptp(w["x"]), np.ptp(w["y"]), h) * (1 + 2.0 ** -20)  # the plan's root box side
+    s = F.Surrogate(w["d"], w["eps"], p=10, rho_max=np.sqrt(2) * Wr * (1 + 1e-9), zeta_max=2 * Wr * (1 + 1e-9),
+                    seed=11)
+    rep = s.train()
+    _say(f"  trained: loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}, val rms {rep['val_rms']:.3e}, "
+         f"{rep['sample_seconds']:.2f}s sampling, {rep['train_seconds']:.2f}s training")
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.choice(n, 32, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=t,
+                               method="table")
+    q = torch.tensor(w["q"][0], device=dev)
+    out = torch.empty_like(q)
+    for prec in (1, 0):
+        plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=192, precision=prec,
+                      mac_d2=4, surrogate=s)
+        st = plan.stats()
+        assert st["surrogate_tasks"] == st["n_sommerfeld_tasks"] > 0
+        assert st["surrogate_pairs"] == st["p2p_reaction_pairs"]
+        plan.eval(q, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            plan.eval(q, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        phi = out.cpu().numpy()
+        plan.close()
+        e = relerr(phi[t], ref)
+        _say(f"  {'FP32' if prec else 'FP64'} form: {e:.3e} vs oracle (32 targets), {ms:.2f} ms per matvec, "
+             f"plan {st['plan_seconds']:.2f}s, check {st['surrogate_check']:.2e}, "
+             f"tasks {st['n_sommerfeld_tasks']}, near pairs {st['p2p_reaction_pairs']}")
+        assert e <= 1e-5
+        assert st["surrogate_check"] < 1e-5
+    s.close()
