@@ -187,12 +187,22 @@ def run_form(fmmlm, w, p, cap, mac, precision, steps, warmup, dev, rhs=1, surrog
             "phi_all": phi}
 
 
-def run_forms(fmmlm, workloads, oracle, dev, steps, warmup, metric_w, p):
+def run_forms(fmmlm, workloads, oracle, dev, steps, warmup, metric_w, p, which="all"):
     """The other two forms on their own workloads, and the initial-value sources compared
     (one JSON object): the batched form on the four-layer workload (64 charge vectors per
     pass), the learned form on the six-region workload, plan times with quadrature, tables
     and the network on the metric workload and the six-region one."""
-    import numpy as np
+    res = {}
+    if which in ("all", "plans"):
+        res.update(_initial_values_3layer(fmmlm, metric_w, p))
+    if which in ("all", "batched"):
+        res.update(_batched_form(fmmlm, workloads, oracle, dev, steps))
+    if which in ("all", "learned"):
+        res.update(_learned_form(fmmlm, workloads, oracle, dev, steps))
+    return res
+
+
+def _initial_values_3layer(fmmlm, metric_w, p):
     res = {}
     # initial values on the metric workload: quadrature vs tables vs network (plan time only)
     tab, t_tab, net, t_net, rep = initial_value_forms(fmmlm, metric_w, p)
@@ -203,6 +213,12 @@ def run_forms(fmmlm, workloads, oracle, dev, steps, warmup, metric_w, p):
     tab.close()
     net.close()
     print(f"[bench] initial values, 3 layers: {res['initial_values_3layer']}", file=sys.stderr, flush=True)
+    return res
+
+
+def _batched_form(fmmlm, workloads, oracle, dev, steps):
+    import numpy as np
+    res = {}
     # batched form: four layers, N = 524288, 64 charge vectors a pass (the table form
     # supplies the plan's initial values and near-field kernels)
     import math
@@ -234,6 +250,12 @@ def run_forms(fmmlm, workloads, oracle, dev, steps, warmup, metric_w, p):
                       "stage_ms": b["stages"], "roofline": roof,
                       "batch_variant": bst["batch_variant"]}
     print(f"[bench] batched: {res['batched']['value']:.1f} matvec/s, errors {errs}", file=sys.stderr, flush=True)
+    return res
+
+
+def _learned_form(fmmlm, workloads, oracle, dev, steps):
+    import numpy as np
+    res = {}
     # learned form: six regions, N = 2097152, the network serving every initial value
     w5 = workloads.config(4)
     tab5, t_tab5, net5, t_net5, rep5 = initial_value_forms(fmmlm, w5, 10)
@@ -348,6 +370,9 @@ def main():
                          "with quadrature)")
     ap.add_argument("--solve-n", type=int, default=1048576,
                     help="panels of the capacitance-style GMRES solve (0: skip it)")
+    ap.add_argument("--forms-only", default=None, choices=["all", "batched", "learned", "plans"],
+                    help="run only these parts of the forms section and print them as one JSON line "
+                         "(profiling runs)")
     ap.add_argument("--forms", type=int, default=1,
                     help="1: also run the batched form (four layers, 64 vectors) and the learned form "
                          "(six regions, N = 2M) and compare the initial-value sources (0: skip)")
@@ -365,6 +390,12 @@ def main():
     w = workloads.config(args.workload)
     p = args.p or w["p"]
     dev = torch.device("cuda:0")
+    if args.forms_only:
+        import oracle
+        calibration_copy(dev)
+        print(json.dumps(run_forms(fmmlm, workloads, oracle, dev, args.steps, args.warmup, w, p,
+                                   which=args.forms_only)))
+        return
     n = len(w["x"])
     print(f"[bench] workload {w['name']} N={n} p={p} mac={args.mac}", file=sys.stderr, flush=True)
     calibration_copy(dev)

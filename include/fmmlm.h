@@ -263,10 +263,11 @@ typedef struct {
   double nearfield_seconds;    /*   reaction near-field kernel values */
   int64_t surrogate_tasks;     /* learned form: Sommerfeld tasks served by the network ... */
   int64_t surrogate_pairs;     /*   ... and near-field pairs (the rest took the quadrature) */
-  double surrogate_check;      /*   learned form against the quadrature on up to 256 sampled
-                                    tasks: the largest R1 max_{N,M} 0.87^N |difference of
-                                    S^N I_{N,M}|, R1 = |(rho, z + zinf)| (the error relative to
-                                    the interaction 1/R1 that the operator carries) */
+  double surrogate_check;      /*   learned (or table) form against the quadrature on up to
+                                    256 sampled tasks: the largest R1 max_{N,M} 0.87^N
+                                    |difference of S^N I_{N,M}|, R1 = |(rho, z + zinf)| (the error
+                                    relative to the interaction 1/R1 that the operator carries).
+                                    Above 1e-5 the plan rejects the form (surrogate_rejected) */
   int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one tile) ... */
   int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
                                     (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
@@ -280,7 +281,9 @@ typedef struct {
                                   32; slices of 16 otherwise, and where the padded column count is
                                   not a multiple of 32; (p+1)^2 <= 128 only, else unused) */
   int32_t batch_variant;       /* batched FP32 form: M2L variant picked by the autotuner ... */
-  int32_t reserved_stats2;
+  int32_t surrogate_rejected;  /* 1 when the plan's surrogate (network or tables) missed
+                                    surrogate_check <= 1e-5 on the plan's sampled tasks and the
+                                    quadrature served the whole plan instead */
   double batch_variant_ms[10]; /*   ... and one launch's time in each: variant v has the tile shape
                                   v % 5 (outputs per wave over operator rows x 64 vectors; 0: 4 waves
                                   of 64 x 32, 1: 8 of 32 x 32, 2: 8 of 64 x 16, 3: 16 of 32 x 16,

@@ -256,6 +256,11 @@ struct Builder {
   }
 };
 
+// Largest deviation of the learned or table form from the quadrature on a
+// plan's sampled tasks (interaction units, fmmlm_stats.surrogate_check) that the
+// plan accepts; above it the quadrature serves the plan.
+constexpr double kSurrogateBound = 1e-5;
+
 double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1152,6 +1157,16 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     P->stats.table_seconds = seconds_since(ts);
     if (rc == FMMLM_OK && sur) rc = surrogate_check(P, comps, B.tasks, tables, st);
+    if (rc == FMMLM_OK && sur && !(P->stats.surrogate_check <= kSurrogateBound)) {
+      // the learned or table form misses its bound on this plan's own tasks: the
+      // quadrature serves every initial value and near-field kernel instead
+      P->stats.surrogate_rejected = 1;
+      P->stats.surrogate_tasks = 0;
+      sur = nullptr;
+      const auto tq = std::chrono::steady_clock::now();
+      rc = gpu_sommerfeld_tables(P->medium, comps, B.tasks, 2 * p, tables, st);
+      P->stats.table_seconds += seconds_since(tq);
+    }
     if (rc) {
       hipFree(tables);
       return rc;

@@ -74,7 +74,7 @@ class Stats(ctypes.Structure):
                 ("m2l_steps", ctypes.c_int64), ("m2l_tile_cols", ctypes.c_int32),
                 ("m2l_variant", ctypes.c_int32), ("m2l_top_pairs", ctypes.c_int64),
                 ("m2l_variant_ms", ctypes.c_double * 6), ("batch_variant", ctypes.c_int32),
-                ("reserved_stats2", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10),
+                ("surrogate_rejected", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10),
                 ("m2l_eval_ms", ctypes.c_double * 6), ("p2p_split_ms", ctypes.c_double * 5),
                 ("p2p_split_pct", ctypes.c_int32), ("batch_min_rhs", ctypes.c_int32)]
 

@@ -243,12 +243,45 @@ def test_fmm_with_surrogate_vs_oracle(trained, ladder_only, F, W, oracle_mod):
              f"learned tasks {st['surrogate_tasks']} pairs {st['surrogate_pairs']}/{st['p2p_reaction_pairs']} "
              f"check {st['surrogate_check']:.2e}")
         if sur is not None:
-            assert st["surrogate_tasks"] > 0.9 * st["n_sommerfeld_tasks"]
+            # a form is kept when its plan check meets 1e-5 (interaction units), else the
+            # quadrature serves the plan (the ladder alone sits at about that bound)
+            if st["surrogate_check"] <= 1e-5:
+                assert st["surrogate_rejected"] == 0 and st["surrogate_tasks"] > 0.9 * st["n_sommerfeld_tasks"]
+            else:
+                assert st["surrogate_rejected"] == 1 and st["surrogate_tasks"] == 0
         if sur is s:
-            assert st["surrogate_check"] < 1e-5
+            assert st["surrogate_check"] < 1e-5 and st["surrogate_rejected"] == 0
     assert errs["quadrature"] < 1e-6
     assert errs["ladder+net"] < 1e-5
 
+
+
+def test_plan_rejects_a_form_that_misses_its_bound(trained, F, W):
+    """A network with scrambled weights misses the plan's check (<= 1e-5 in interaction
+    units): the plan reports the rejection and the quadrature serves it, bit for bit as a
+    plan without the surrogate."""
+    import torch
+    s, rep, w0 = trained
+    w = W.config(4, n=3000, seed=21)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=24)
+    bad = F.Surrogate(plan=plan, seed=3)
+    bad.params(np.random.default_rng(9).normal(0, 3.0, s.params().size).astype(np.float32))
+    q = torch.tensor(w["q"][0], device="cuda:0")
+    ref = plan.eval(q).cpu().numpy()
+    plan.close()
+    pl = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=24, surrogate=bad)
+    st = pl.stats()
+    phi = pl.eval(q).cpu().numpy()
+    pl.close()
+    bad.close()
+    _say(f"  scrambled network: check {st['surrogate_check']:.2e}, rejected {st['surrogate_rejected']}")
+    assert st["surrogate_check"] > 1e-5 and st["surrogate_rejected"] == 1 and st["surrogate_tasks"] == 0
+    np.testing.assert_array_equal(phi, ref)
+    # the trained network passes and is kept
+    pl = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=24, surrogate=s)
+    st = pl.stats()
+    pl.close()
+    assert st["surrogate_rejected"] == 0 and st["surrogate_tasks"] > 0
 
 def test_gain_over_quadrature(trained, F, W):
     """What the network buys: initial values of the Sommerfeld integrals and the
