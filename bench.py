@@ -27,24 +27,26 @@ METRIC = "FMM matvecs/sec at N=1M 3-layer p=10 vs plain FP64 GPU FMM at <=1e-5 r
 # PMC summaries of HBM traffic per stage's kernel (see measured_traffic)
 TRAFFIC_FILES = {
     "m2l": os.path.join(ROOT, "profiles", "m2l_mfma32_3layer_N1048576_p10_traffic.md"),
-    "p2p_free": os.path.join(ROOT, "profiles", "p2p_leaf_3layer_N1048576_p10_traffic.md"),
+    "p2p_free": os.path.join(ROOT, "profiles", "p2p_mutual_3layer_N1048576_p10_traffic.md"),
     "m2l_batch": os.path.join(ROOT, "profiles", "m2l_batch32_4layer_N524288_p10_rhs64_traffic.md"),
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_1908_10863_amd", "csrc", "fmm.hip")
 # kernel that carries each stage of the FP32 form (one launch per evaluation)
-STAGE_KERNEL = {"m2l": "m2l_mfma32_kernel", "p2p_free": "p2p_leaf_kernel<float>"}
+STAGE_KERNEL = {"m2l": "m2l_mfma32_kernel", "p2p_free": "p2p_mutual_kernel<float> + p2p_combine_kernel<float>"}
 CALIB_BYTES = 256 << 20  # plain device-to-device copy that scales the PMC byte counters
 PEAK_FP64 = 78.6e12  # MI355X FP64, vector and dense matrix (published), FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32, vector and dense matrix (published), FLOP/s
 # Plain VALU issue rate with packed FP32 off (as the library is compiled): 256 CUs x 4 SIMDs x 16
-# lanes x 2.4 GHz lane-instructions per second.  The free P2P inner loop takes 8 VALU
-# instructions per pair (3 sub, mul and 2 fma for r^2, rsq, fma into the sum; the
-# zero-distance compare and select run only over a leaf's own points) for the 11 flops
-# counted per pair.  The ratio of the achieved rate to 11/8 of the lane rate is reported
-# beside the roofline as an issue-efficiency figure; the roofline itself is priced against
-# the published peak of the stage's arithmetic.
+# lanes x 2.4 GHz lane-instructions per second.  The free P2P evaluates each pair of distinct
+# leaves once for both of its sums: 9 VALU instructions per point pair (3 sub, mul and 2 fma
+# for r^2, rsq, an fma into each side's sum), 4.5 per ordered pair, for the 11 flops counted per
+# ordered pair (the algorithmic count: both directions of the direct sum).  The leaf's own
+# points (a few percent of the pairs) take 8 plus a zero-distance select per ordered pair.
+# The ratio of the achieved rate to 11/4.5 of the lane rate is reported beside the roofline
+# as an issue-efficiency figure; the roofline itself is priced against the published peak of
+# the stage's arithmetic.
 VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
-P2P_INSTR_PER_PAIR = 8
+P2P_INSTR_PER_PAIR = 4.5
 P2P_FLOPS_PER_PAIR = 11
 ISSUE_CEILING = {"p2p_free": VALU_LANE_RATE / P2P_INSTR_PER_PAIR * P2P_FLOPS_PER_PAIR}
 

@@ -1055,7 +1055,109 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   for (int64_t li = 0; li < P->nleaves; ++li)
     if (pptr[li + 1] > pptr[li]) plv.push_back((int32_t)li);
   P->n_pl_leaves = (int64_t)plv.size();
-  P->pl_split = P->n_pl_leaves;  // all at the fork until the evaluation-level tuner decides
+  // ---- mutual free P2P units.  Every free-space pair of points is in both
+  // leaves' lists (the list relation is symmetric); the pair of a leaf A and a
+  // list range C is evaluated once, by A's units when C lies after A in tree
+  // order (its 1/r serves both sums), and skipped in the units of C's leaves.
+  // The leaf's own range stays one way (first range of each unit).  A unit
+  // covering leaf c in its later ranges fills one row of c's source-side sums.
+  std::vector<int32_t> mleaf, mtb, mrptr(1, 0), mrng, cbn(P->nleaves, -1);
+  std::vector<int64_t> mboff, mwork;
+  // (unit's first position of the leaf, leaf, row of the leaf)
+  std::vector<std::array<int64_t, 3>> segs;
+  int64_t npos = 0;
+  {
+    const int tpb = P->fp32 ? kPLUnitTargetsF32 : kPLUnitTargetsF64;
+    std::vector<std::pair<int64_t, int32_t>> lstart;  // (first point, leaf list index)
+    for (int64_t li = 0; li < P->nleaves; ++li)
+      if (B.boxes[leaves[li]].count > 0) lstart.push_back({B.boxes[leaves[li]].start, (int32_t)li});
+    std::sort(lstart.begin(), lstart.end());
+    std::vector<std::pair<int64_t, int64_t>> up;
+    for (int64_t li = 0; li < P->nleaves; ++li) {
+      const HBox& A = B.boxes[leaves[li]];
+      if (A.count <= 0 || pptr[li + 1] == pptr[li]) continue;
+      up.clear();
+      bool self = false;
+      for (auto& pr : B.p2p_free[leaves[li]]) {
+        if (pr.first == A.start) {
+          if (pr.second != A.count) {
+            set_last_error("internal: free P2P range at a leaf's start is not the leaf");
+            return FMMLM_EUNSUPPORTED;
+          }
+          self = true;
+        } else if (pr.first > A.start) {
+          up.push_back({pr.first, pr.second});
+        }
+      }
+      if (!self) {
+        set_last_error("internal: leaf without its own free P2P range");
+        return FMMLM_EUNSUPPORTED;
+      }
+      if (cbn[li] < 0) cbn[li] = 0;
+      std::sort(up.begin(), up.end());
+      std::vector<std::pair<int64_t, int64_t>> merged;  // contiguous ranges joined
+      for (auto& r : up) {
+        if (!merged.empty() && merged.back().first + merged.back().second == r.first)
+          merged.back().second += r.second;
+        else
+          merged.push_back(r);
+      }
+      int64_t mtot = 0;
+      for (auto& r : merged) mtot += r.second;
+      for (int64_t tb = 0; tb < A.count; tb += tpb) {
+        const int64_t tcp = std::min<int64_t>(tpb, A.count - tb);
+        mleaf.push_back((int32_t)li);
+        mtb.push_back((int32_t)tb);
+        mrng.push_back((int32_t)A.start);
+        mrng.push_back((int32_t)A.count);
+        for (auto& r : merged) {
+          mrng.push_back((int32_t)r.first);
+          mrng.push_back((int32_t)r.second);
+        }
+        mrptr.push_back((int32_t)(mrng.size() / 2));
+        mwork.push_back(tcp * (A.count + mtot));
+        mboff.push_back(npos);
+        for (auto& r : merged) {
+          auto it = std::lower_bound(lstart.begin(), lstart.end(), std::make_pair(r.first, (int32_t)-1));
+          int64_t covered = 0;
+          for (; it != lstart.end() && it->first < r.first + r.second; ++it) {
+            const int32_t c = it->second;
+            const int64_t cn = B.boxes[leaves[c]].count;
+            if (cbn[c] < 0) cbn[c] = 0;
+            segs.push_back({npos + covered, c, cbn[c]++});
+            covered += cn;
+          }
+          if (covered != r.second) {
+            set_last_error("internal: free P2P range is not a union of leaves");
+            return FMMLM_EUNSUPPORTED;
+          }
+          npos += r.second;
+        }
+      }
+    }
+  }
+  P->n_mu_units = (int64_t)mleaf.size();
+  P->pl_split = P->n_mu_units;  // all at the fork until the evaluation-level tuner decides
+  // launch order: most pairs first, so that the launch does not end on a few
+  // long units (each unit writes its own slots: the order leaves results alone)
+  std::vector<int32_t> morder(mleaf.size());
+  for (size_t u = 0; u < morder.size(); ++u) morder[u] = (int32_t)u;
+  std::stable_sort(morder.begin(), morder.end(), [&](int32_t a, int32_t b) { return mwork[a] > mwork[b]; });
+  std::vector<int64_t> cbbase(P->nleaves, 0);
+  int64_t nbvals = 0;
+  for (int64_t li = 0; li < P->nleaves; ++li) {
+    cbbase[li] = nbvals;
+    if (cbn[li] > 0) nbvals += (int64_t)cbn[li] * B.boxes[leaves[li]].count;
+  }
+  if (nbvals >= ((int64_t)1 << 31)) {
+    set_last_error("free P2P: more than 2^31 source-side sums");
+    return FMMLM_EUNSUPPORTED;
+  }
+  std::vector<int32_t> mbidx(std::max<int64_t>(npos, 1), 0);
+  for (auto& sg : segs) {
+    const int64_t c = sg[1], cn = B.boxes[leaves[c]].count, base = cbbase[c] + sg[2] * cn;
+    for (int64_t i = 0; i < cn; ++i) mbidx[sg[0] + i] = (int32_t)(base + i);
+  }
   P->stats.p2p_free_pairs = B.free_pairs;
   P->stats.p2p_reaction_pairs = B.reac_pairs;
   // ---- leaf of every tree point, free-space point ranges
@@ -1101,6 +1203,18 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   UP(bparent, bparent); UP(bchild0, bchild0); UP(bnchild, bnchild); UP(leaves, leaves);
   UP(m2l_ptr, mptr); UP(m2l_nfree, mnfree); UP(m2l_src, msrc); UP(m2l_op, mop);
   UP(p2p_ptr, pptr); UP(p2p_src, psrc); UP(pl_leaves, plv); UP(rp_ptr, rptr); UP(rp_src, rsrc); UP(rp_voff, rvoff);
+  UP(mu_order, morder); UP(mu_leaf, mleaf); UP(mu_tb, mtb); UP(mu_rptr, mrptr); UP(mu_rng, mrng); UP(mu_boff, mboff);
+  UP(mu_bidx, mbidx); UP(cb_base, cbbase); UP(cb_n, cbn);
+  if ((rc = dev_alloc(P, &P->mu_a, (size_t)P->NP))) return rc;
+  if (P->fp32) {
+    float* b32 = nullptr;
+    if ((rc = dev_alloc(P, &b32, (size_t)std::max<int64_t>(nbvals, 1)))) return rc;
+    P->mu_b = b32;
+  } else {
+    double* b64 = nullptr;
+    if ((rc = dev_alloc(P, &b64, (size_t)std::max<int64_t>(nbvals, 1)))) return rc;
+    P->mu_b = b64;
+  }
   UP(rp_row, rrow); UP(rp_units, runits);
   P->n_rp_units = (int64_t)(runits.size() / 3);
   if ((rc = dev_alloc(P, &P->Prp, (size_t)std::max<int64_t>(nrows, 1)))) return rc;

@@ -23,6 +23,10 @@ constexpr int kSpItemRounds = 4;
 constexpr int kBatchTopItem = 24;
 // reaction P2P: target rows per work unit (one wave, 8 lanes a row)
 constexpr int kRPUnitRows = 8;
+// free P2P (single vector): targets of one work unit, 16 lane slots x targets
+// a lane (8 in FP32, 4 in FP64)
+constexpr int kPLUnitTargetsF32 = 128;
+constexpr int kPLUnitTargetsF64 = 64;
 
 // ---- small complex type (device and host) ------------------------------------
 struct cplx {
@@ -202,8 +206,26 @@ struct fmmlm_plan_s {
   // P2P free, CSR over leaves
   int32_t *p2p_ptr = nullptr;      // [nleaves + 1]
   int32_t *p2p_src = nullptr;      // [2 * entries] (start, count)
-  int32_t *pl_leaves = nullptr;    // leaf list indices with free-space P2P entries
+  int32_t *pl_leaves = nullptr;    // leaf list indices with free-space P2P entries (batched form)
   int64_t n_pl_leaves = 0;
+  // single-vector free P2P, mutual form: a unit is up to kPLUnitTargets(form)
+  // targets of one leaf against the leaf itself (one way) and the ranges after
+  // it in tree order (both ways).  Target-side sums go to mu_a (per point);
+  // source-side sums to mu_b, where leaf c holds cb_n[c] rows of its count of
+  // values from cb_base[c] (one row per unit that covers it, in unit order),
+  // at the index mu_bidx gives for each position of a unit's ranges after the
+  // first; a combine pass adds a point's values in that order
+  int64_t n_mu_units = 0;
+  int32_t *mu_order = nullptr;     // [n_mu_units] launch order (most pairs first)
+  int32_t *mu_leaf = nullptr, *mu_tb = nullptr;  // [n_mu_units] leaf list index, first target
+  int32_t *mu_rptr = nullptr;      // [n_mu_units + 1] into mu_rng; a unit's first range is its own leaf
+  int32_t *mu_rng = nullptr;       // [2 * ranges] (start, count)
+  int64_t *mu_boff = nullptr;      // [n_mu_units] the unit's first position in mu_bidx
+  int32_t *mu_bidx = nullptr;      // [positions] index into mu_b
+  int64_t *cb_base = nullptr;      // [nleaves] first row of the leaf in mu_b
+  int32_t *cb_n = nullptr;         // [nleaves] rows of the leaf (-1: no free P2P)
+  double *mu_a = nullptr;          // [NP]
+  void *mu_b = nullptr;            // float (FP32 form) or double
   // P2P reaction, CSR over leaves
   int32_t *rp_ptr = nullptr;       // [nleaves + 1]
   int32_t *rp_src = nullptr;       // [2 * entries] (start, count)
@@ -235,7 +257,7 @@ struct fmmlm_plan_s {
   hipStream_t s_near = nullptr, s_top = nullptr;
   hipEvent_t ev_q = nullptr, ev_m = nullptr, ev_near = nullptr, ev_top = nullptr;
   hipEvent_t ev_l = nullptr;       // main M2L launched (the rest of the near field may start)
-  int64_t pl_split = 0;            // free P2P leaves launched at the fork; the rest after the main M2L
+  int64_t pl_split = 0;            // free P2P units launched at the fork; the rest after the main M2L
   // graph mode: the captured evaluation and its arguments
   hipGraphExec_t gexec = nullptr;
   fmmlm::GraphKey gkey;

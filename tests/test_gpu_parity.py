@@ -463,6 +463,35 @@ def test_pure_near_field_matches_direct_sum(dev, F, oracle_mod):
         assert relerr(phi, ref) < 1e-13
 
 
+@pytest.mark.parametrize("precision,n,cap", [(0, 2400, 220), (1, 2400, 220), (0, 6400, 500), (1, 6400, 500)])
+def test_near_field_pairs_both_ways(dev, F, oracle_mod, precision, n, cap):
+    """One interface, each layer's points filling its tree's root cube: the free-space
+    trees stop at depth one, the eight leaves of a tree are mutually adjacent, and every
+    free-space pair is near field.  A pair of distinct leaves is evaluated once for both
+    of its sums; leaves of about n/16 points span several work units (128 targets in
+    the FP32 form, 64 in FP64).  The free part equals the direct sum."""
+    import torch
+    _say(f"near field both ways precision={precision} n={n} cap={cap}")
+    rng = np.random.default_rng(31 + n)
+    h = n // 2
+    x = rng.uniform(-0.5, 0.5, n)
+    y = rng.uniform(-0.5, 0.5, n)
+    z = np.concatenate([rng.uniform(1e-3, 1.0, h), -rng.uniform(1e-3, 1.0, n - h)])
+    layer = np.concatenate([np.zeros(h, np.int32), np.ones(n - h, np.int32)])
+    d, eps = np.array([0.0]), np.array([1.0, 3.0])
+    qv = rng.uniform(-1, 1, n)
+    plan = F.Plan(d, eps, x, y, z, layer, p=8, leaf_cap=cap, precision=precision)
+    st = plan.stats()
+    phi = plan.eval(torch.tensor(qv, dtype=torch.float64, device=dev), parts=1).cpu().numpy()
+    plan.close()
+    assert st["m2l_free_pairs"] == 0
+    assert st["p2p_free_pairs"] == h * h + (n - h) * (n - h)  # every ordered pair, self pairs included
+    ref = oracle_mod.potential(d, eps, x, y, z, layer, qv, parts=1)
+    e = relerr(phi, ref)
+    _say(f"  {e:.3e}")
+    assert e < (1e-13 if precision == 0 else 2e-6)
+
+
 def test_homogeneous_medium_is_coulomb(dev, F):
     """All permittivities equal: the layered FMM reproduces the plain Coulomb sum over
     all charges across layers."""
