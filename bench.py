@@ -506,7 +506,9 @@ def main():
                    "m2l_variant_ms": [round(x, 4) for x in st["m2l_variant_ms"]],
                    "m2l_eval_ms": [round(x, 4) for x in st["m2l_eval_ms"]],
                    "p2p_split_pct": st["p2p_split_pct"],
-                   "p2p_split_ms": [round(x, 4) for x in st["p2p_split_ms"]]},
+                   "p2p_split_ms": [round(x, 4) for x in st["p2p_split_ms"]],
+                   "p2p_lds_reserve": st["p2p_lds_reserve"],
+                   "p2p_reserve_ms": [round(x, 4) for x in st["p2p_reserve_ms"]]},
     }
     print(json.dumps(rec))
 

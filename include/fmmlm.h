@@ -299,6 +299,12 @@ typedef struct {
   int32_t batch_min_rhs;       /* batched passes narrower than this run vector by vector
                                   (timed at plan time: one batched pass of max_rhs vectors
                                   against one single-vector evaluation) */
+  int32_t p2p_lds_reserve;     /* FP32 form: bytes of LDS each free P2P block reserves beyond its
+                                  own use when it runs beside the far field (unprofiled
+                                  evaluations): the fastest of the candidates timed in
+                                  p2p_reserve_ms; it bounds the P2P blocks a CU holds and leaves
+                                  room for far-field blocks beside them */
+  double p2p_reserve_ms[3];    /*   ... whole-evaluation times with 28672, 40960 and 0 bytes */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);

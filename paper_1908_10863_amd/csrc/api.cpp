@@ -744,10 +744,14 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       P->n_sp_boxes = (int64_t)spb.size();
       if (int rc0 = dev_upload(P, &P->sp_boxes, spb, st)) return rc0;
       // work items: runs of kSpItemRounds rounds of sp_ne entries (the block's
-      // threads hold sp_ne entries x nc coefficients; LDS holds their source
-      // expansions, operator tables and sums, at most 60 KiB)
+      // threads hold sp_ne entries x the coefficients (n, m >= 0) in groups of
+      // four orders; LDS holds their source expansions, operator tables and
+      // sums, at most 60 KiB)
       const int nc = P->nc, ng = P->ng, nr = (P->p + 1) * (P->p + 1);
-      P->sp_ne = std::max(1, std::min(kSpThreads / nc, 61440 / ((nr + ng + nc) * 16)));
+      int tps = 0;
+      for (int n = 0; n <= P->p; ++n) tps += (n + 4) / 4;
+      P->sp_ne = std::max(1, std::min(kSpThreads / tps, 61440 / ((nr + ng + nc) * 16)));
+      P->sp_threads = (P->sp_ne * tps + 63) / 64 * 64;
       const int run = kSpItemRounds * P->sp_ne;
       std::vector<int32_t> items, iptr(1, 0);
       for (const int32_t b : spb) {
@@ -1001,6 +1005,28 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       P->xl_l2l[l] = q;
     }
     P->xl_units = (int64_t)(xus.size() / 2);
+    // translations whose results nothing reads are skipped: M2M into level l
+    // only if some M2L takes a source on level l or above it (through later
+    // M2M), L2L out of level l only if level l or a level above it receives an
+    // M2L (otherwise its local expansions are zero).  With mac_d2 = 4 the root
+    // is in no M2L pair, so M2M into it and L2L out of it go.
+    {
+      std::vector<char> src_on(P->maxlev + 1, 0), tgt_on(P->maxlev + 1, 0);
+      for (int64_t b = 0; b < P->NB; ++b)
+        for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
+          tgt_on[B.boxes[b].level] = 1;
+          src_on[B.boxes[msrc[e]].level] = 1;
+        }
+      P->xl_need_m2m.assign(P->maxlev + 1, 0);
+      P->xl_need_l2l.assign(P->maxlev + 1, 0);
+      char needm = 0, hasl = 0;
+      for (int l = 0; l <= P->maxlev; ++l) {
+        needm = needm || src_on[l];
+        P->xl_need_m2m[l] = needm;  // M2M into level l
+        if (l >= 1) P->xl_need_l2l[l] = hasl;  // L2L from level l - 1 into level l
+        hasl = hasl || tgt_on[l];
+      }
+    }
     int rc0;
 #define UPX(field, vec) if ((rc0 = dev_upload(P, &P->field, vec, st))) return rc0
     UPX(xl_step_op, xop); UPX(xl_step_kind, xkind); UPX(xl_step_src, xsrc); UPX(xl_step_mask, xmask);

@@ -18,7 +18,7 @@ constexpr int kPMax = FMMLM_PMAX;
 constexpr int kMaxLevel = 20;  // 21-bit quantisation per axis
 // sparse top-level M2L: threads of a block, rounds of entries per work item
 constexpr int kSpThreads = 512;
-constexpr int kSpItemRounds = 4;
+constexpr int kSpItemRounds = 1;
 // batched FP32 form, FP64 top levels: entries per work item
 constexpr int kBatchTopItem = 24;
 // reaction P2P: target rows per work unit (one wave, 8 lanes a row)
@@ -153,6 +153,7 @@ struct fmmlm_plan_s {
   // and their own tiles; per level (first tile, first unit, end tile, end unit)
   double* Txl = nullptr;           // [16][nrk][32 mrt]
   std::vector<std::array<int64_t, 4>> xl_m2m, xl_l2l;
+  std::vector<char> xl_need_m2m, xl_need_l2l;  // per level: the translation into it is needed
   int64_t xl_units = 0;
   int32_t *xl_step_op = nullptr, *xl_step_kind = nullptr, *xl_step_src = nullptr, *xl_step_mask = nullptr;
   int32_t *xl_unit_s = nullptr, *xl_unit_mask = nullptr, *xl_tile_unit_ptr = nullptr, *xl_tile_tgt = nullptr;
@@ -163,7 +164,8 @@ struct fmmlm_plan_s {
   // items (sp_item_ptr), partial sums per item [n_sp_items][nc] complex
   int32_t *sp_items = nullptr, *sp_item_ptr = nullptr;
   int64_t n_sp_items = 0;
-  int sp_ne = 1;                   // entries per round of an item's block
+  int sp_ne = 1;                   // entries per round of an item's block ...
+  int sp_threads = 64;             //   ... and its threads (a multiple of 64)
   double* Psp = nullptr;
   // FP32 form: operator-major chunks; per target box its slots (unit * tile_cols + column)
   int32_t *slot_boxes = nullptr, *slot_ptr = nullptr, *slots = nullptr;
@@ -258,6 +260,7 @@ struct fmmlm_plan_s {
   hipEvent_t ev_q = nullptr, ev_m = nullptr, ev_near = nullptr, ev_top = nullptr;
   hipEvent_t ev_l = nullptr;       // main M2L launched (the rest of the near field may start)
   int64_t pl_split = 0;            // free P2P units launched at the fork; the rest after the main M2L
+  size_t pl_pad = 28672;           // LDS a free P2P block reserves beside the far field (tuned)
   // graph mode: the captured evaluation and its arguments
   hipGraphExec_t gexec = nullptr;
   fmmlm::GraphKey gkey;
