@@ -745,12 +745,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       if (int rc0 = dev_upload(P, &P->sp_boxes, spb, st)) return rc0;
       // work items: runs of kSpItemRounds rounds of sp_ne entries (the block's
       // threads hold sp_ne entries x the coefficients (n, m >= 0) in groups of
-      // four orders; LDS holds their source expansions, operator tables and
-      // sums, at most 60 KiB)
+      // four orders; LDS holds their source expansions and operator tables,
+      // then their sums, at most 60 KiB)
       const int nc = P->nc, ng = P->ng, nr = (P->p + 1) * (P->p + 1);
       int tps = 0;
       for (int n = 0; n <= P->p; ++n) tps += (n + 4) / 4;
-      P->sp_ne = std::max(1, std::min(kSpThreads / tps, 61440 / ((nr + ng + nc) * 16)));
+      P->sp_ne = std::max(1, std::min(kSpThreads / tps, 61440 / (std::max(nr + ng, nc) * 16)));
       P->sp_threads = (P->sp_ne * tps + 63) / 64 * 64;
       const int run = kSpItemRounds * P->sp_ne;
       std::vector<int32_t> items, iptr(1, 0);
