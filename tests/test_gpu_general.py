@@ -4,8 +4,10 @@ direct solve of the general interface system.
 * a = 1, b = eps: the same evaluation as the classic plan, bit for bit.
 * Three layers, a = (1, 0.5, 2), b = (1, 3, 6); FP64 form p = 12, mac 6,
   N = 1500: rel L2 <= 1e-6 on 60 targets (the oracle's quadrature sum).
-* Four layers, seeded a, b; FP32 form p = 10, mac 4, N = 4000: rel L2 <= 2e-5
-  on 40 targets.
+* Four layers, seeded a, b; FP32 form p = 10, mac 4, N = 4000: rel L2 <= 1e-5
+  (the form's bar) on 40 targets.  Measured 1.49e-6, and 1.47e-6 for the FP64
+  form at the same order and MAC: the truncation at p = 10, not the FP32
+  arithmetic, sets it (2.7e-7 at p = 12, 1.1e-7 at p = 14).
 * The learned form is refused for a general plan.
 """
 import sys
@@ -68,7 +70,7 @@ def test_general_conditions_vs_oracle(dev, F, oracle_mod, case):
         rng = np.random.default_rng(23)
         a, b = rng.uniform(0.4, 2.5, 4), rng.uniform(0.8, 10.0, 4)
         kw = dict(p=10, leaf_cap=64, precision=1, mac_d2=4)
-        nt, tol = 40, 2e-5
+        nt, tol = 40, 1e-5
     _say(f"general conditions {case}: a={np.round(a, 3)} b={np.round(b, 3)}")
     pl = F.Plan(w["d"], b, w["x"], w["y"], w["z"], w["layer"], interface_a=a, **kw)
     phi = pl.eval(torch.tensor(w["q"][0], device=dev)).cpu().numpy()
