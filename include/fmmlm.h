@@ -64,7 +64,8 @@ typedef struct fmmlm_surrogate_s* fmmlm_surrogate_t;
 typedef struct {
   int32_t leaf_cap;        /* a box is split while it holds more points (default 64) */
   int32_t precision;       /* FMMLM_FP64 (default) or FMMLM_FP32_COMPENSATED */
-  int32_t fp64_top_levels; /* FP32 form: tree levels 0..k-1 kept in FP64 (default 3) */
+  int32_t fp64_top_levels; /* tree levels 0..k-1 whose M2L runs in the sparse FP64 kernel
+                              (default 3); the FP32 form keeps these levels in FP64 */
   int32_t max_rhs;         /* largest nrhs accepted by eval (default 1).  Above 1 the plan
                               holds expansions for G = min(max_rhs, 64) charge vectors and
                               evaluates them together (batched M2L on the matrix cores in
@@ -272,8 +273,8 @@ typedef struct {
   int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
                                     (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
   int32_t m2l_variant;         /* FP32 form: M2L tile shape picked by the plan's autotuner (see m2l_eval_ms) */
-  int64_t m2l_top_pairs;       /* FP32 form: M2L pairs on the levels kept in FP64, run by the
-                                    "M2L top" stage (0 in the FP64 form) */
+  int64_t m2l_top_pairs;       /* M2L pairs on the top levels (fp64_top_levels), run by the
+                                    sparse FP64 kernel in the "M2L top" stage */
   double m2l_variant_ms[6];    /* autotuner: time of one M2L launch alone in each tile shape (outputs
                                   per wave, rows x columns, operator columns per LDS slice; 0: 16
                                   waves of 32 x 32, slices of 32; 1: 8 of 32 x 64; 2: 8 of 64 x 32;
@@ -589,11 +590,12 @@ int fmm_layered_density(int32_t n_interfaces, const double* z_interfaces, const 
  * next max_evals evaluations of the plan record a HIP event on their stream
  * before the first stage and after every stage (FMMLM_NSTAGES stages, in the
  * order gather, P2M, M2M, M2L top, M2L, M2L reduce, L2L, L2P, P2P free,
- * P2P reaction, combine).  "M2L" is one kernel launch: the main M2L GEMM (the
- * matrix-core kernel below the FP64 levels in the FP32 form, the FP64 kernel
- * over every level otherwise); "M2L top" clears the local expansions and, in
- * the FP32 form, runs the FP64 levels (sparse kernel) and converts the
- * multipole expansions.
+ * P2P reaction, combine).  "M2L" is one kernel launch: the operator-major M2L
+ * chunks of the levels below the top ones (FP32 matrix cores in the FP32 form,
+ * FP64 matrix cores in the FP64 form); "M2L top" clears the local expansions,
+ * runs the top levels (sparse FP64 kernel) and, in the FP32 form, converts the
+ * multipole expansions to FP32; "M2L reduce" adds each target's chunk
+ * products.
  * profile_end synchronises the device, writes the summed milliseconds of each
  * stage over the recorded evaluations to stage_ms[FMMLM_NSTAGES] (host), the
  * number of recorded evaluations to *n_evals, and stops recording.

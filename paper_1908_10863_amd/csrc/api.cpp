@@ -703,8 +703,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->n_free_ops = nfreeops;
     P->nops = nfreeops + (int64_t)B.reac_task.size();
   }
-  // ---- M2L tiles: up to tile_cols target boxes per tile; one step per
-  // operator present in the tile
+  // ---- M2L steps: the top levels (few boxes, many distinct operators) go to
+  // the sparse FP64 kernel, the levels below them operator-major: chunks of up
+  // to tile_cols pairs of one operator, each a tile of its own with one step
   std::vector<int32_t> tptr(1, 0), ttgt, tlev, sop, skind, ssrc, smask, us, umask, tuptr;
   {
     {
@@ -717,22 +718,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     const int TBc = P->tile_cols;
     const int nfo = (int)P->n_free_ops;
-    std::vector<int> slot(std::max<int64_t>(P->nops, 1), -1);
-    std::vector<int> used;
-    // Four groups of tiles, in this order: free space on the FP64 levels,
-    // reaction on the FP64 levels, free space on the other levels, reaction on
-    // the other levels (in the FP64 form every level is an FP64 level).  Within
-    // a group every target box is in at most one tile.  Free-space tiles hold
-    // boxes of one tree, level and octant class (boxes of one class share their
-    // offsets); reaction tiles hold boxes of one tree, level, xy parity and
-    // height row, since a reaction operator depends on the heights of both
-    // boxes above their interfaces.  Inside a bucket, boxes with the same
-    // operator set are put next to each other.
-    // In the FP32 form the levels kept in FP64 (few boxes, many distinct
-    // operators) run in the sparse FP64 kernel instead of tiles; the FP64 form
-    // tiles every level (its top-level tiles share the one large launch).
-    const int ksp = P->fp32 ? P->opts.fp64_top_levels : 0;
-    const int k64 = P->fp32 ? ksp : P->maxlev + 1;
+    const int ksp = P->opts.fp64_top_levels;  // levels of the sparse kernel
     {
       std::vector<int32_t> spb;
       for (int l = 0; l < std::min(ksp, P->maxlev + 1); ++l)
@@ -767,81 +753,15 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       if (int rc0 = dev_upload(P, &P->sp_item_ptr, iptr, st)) return rc0;
       if (int rc0 = dev_alloc(P, &P->Psp, (size_t)std::max<int64_t>(P->n_sp_items, 1) * nc * 2)) return rc0;
     }
-    P->tile_grp[0] = 0;
-    for (int grp = 0; grp < 4; ++grp) {
-      const bool reac = (grp & 1) != 0;
-      for (int l = ksp; l <= P->maxlev; ++l) {
-        if ((l < k64) != (grp < 2)) continue;
-        if (P->fp32) continue;  // the FP32 form runs these levels operator-major (below)
-        std::vector<std::tuple<uint64_t, uint64_t, int32_t>> key;  // (bucket, operator-set hash, box)
-        std::vector<int> ops;
-        for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b) {
-          ops.clear();
-          for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
-            const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
-            if ((op >= nfo) == reac) ops.push_back(op);
-          }
-          if (ops.empty()) continue;
-          std::sort(ops.begin(), ops.end());
-          uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted operator ids
-          for (int op : ops) {
-            h ^= (uint64_t)(uint32_t)op;
-            h *= 1099511628211ull;
-          }
-          const HBox& bx = B.boxes[b];
-          const uint64_t cls = reac ? (uint64_t)((bx.ix & 1) | ((bx.iy & 1) << 1)) << 32 | (uint64_t)bx.ih
-                                    : (uint64_t)((bx.ix & 1) | ((bx.iy & 1) << 1) | ((bx.ih & 1) << 2)) << 32;
-          key.emplace_back(((uint64_t)bx.tree << 56) | cls, h, (int32_t)b);
-        }
-        std::sort(key.begin(), key.end());
-        // consecutive runs of TBc boxes: small buckets share a tile (the kernels
-        // skip the column groups a step leaves empty)
-        {
-          const size_t k0 = 0, k1 = key.size();
-          for (size_t c0 = k0; c0 < k1; c0 += TBc) {
-            const size_t nc_ = std::min<size_t>(TBc, k1 - c0);
-            tlev.push_back(l);
-            for (size_t c = 0; c < (size_t)TBc; ++c) ttgt.push_back(c < nc_ ? std::get<2>(key[c0 + c]) : -1);
-            used.clear();
-            std::vector<std::vector<int32_t>> cols;
-            for (size_t c = 0; c < nc_; ++c) {
-              const int32_t b = std::get<2>(key[c0 + c]);
-              for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e) {
-                const int op = (mop[e] >= 0) ? mop[e] : ~mop[e];
-                if ((op >= nfo) != reac) continue;
-                if (slot[op] < 0) {
-                  slot[op] = (int)cols.size();
-                  cols.emplace_back(TBc, -1);
-                  used.push_back(op);
-                }
-                cols[slot[op]][c] = msrc[e];
-              }
-            }
-            std::sort(used.begin(), used.end());
-            for (int op : used) {
-              sop.push_back(op);
-              skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
-              const std::vector<int32_t>& cv = cols[slot[op]];
-              ssrc.insert(ssrc.end(), cv.begin(), cv.end());
-              uint32_t msk = 0;  // bit g: a source in columns [8 g, 8 g + 8)
-              for (int c = 0; c < TBc; ++c)
-                if (cv[c] >= 0) msk |= 1u << (c >> 3);
-              smask.push_back((int32_t)msk);
-            }
-            for (int op : used) slot[op] = -1;
-            tptr.push_back((int32_t)sop.size());
-          }
-        }
-      }
-      P->tile_grp[grp + 1] = (int64_t)tlev.size();
-    }
-    // FP32 form, levels below the FP64 ones: operator-major chunks.  All pairs
-    // of one operator (in box units a free-space operator serves every level)
-    // are taken TBc at a time as one step (a tile of its own, one unit); a
-    // target appears at most once per operator, so a chunk's columns are
+    for (int grp = 0; grp <= 4; ++grp) P->tile_grp[grp] = 0;  // no target tiles (M2L is operator-major)
+    // Levels below the sparse ones: operator-major chunks (FP32 products on the
+    // FP32 form's matrix-core kernel, FP64 ones on the FP64 tile GEMM).  All
+    // pairs of one operator (in box units a free-space operator serves every
+    // level) are taken TBc at a time as one step (a tile of its own, one unit);
+    // a target appears at most once per operator, so a chunk's columns are
     // distinct targets.  Each target's outputs are then summed over its slots
     // (unit, column) in operator order by m2l_slot_reduce_kernel.
-    if (P->fp32) {
+    {
       std::vector<std::array<int32_t, 3>> pr;  // (operator, target, source)
       for (int l = ksp; l <= P->maxlev; ++l)
         for (int64_t b = P->lev_off[l]; b < P->lev_off[l + 1]; ++b)
@@ -892,8 +812,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->nsteps = (int64_t)sop.size();
     P->stats.m2l_steps = P->nsteps;
     P->stats.m2l_tile_cols = TBc;
-    // work units of at most kStepsPerUnit steps; units [0, unit_split) belong
-    // to the tiles on FP64 levels (groups 0 and 1)
+    // work units: one step each (the chunks); unit_split is 0 (no target tiles)
     constexpr int kStepsPerUnit = 16;
     tuptr.assign(1, 0);
     for (int64_t t = 0; t < P->ntiles; ++t) {
@@ -910,10 +829,10 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     if (P->ntiles == P->tile_grp[2]) P->unit_split = (int64_t)(us.size() / 2);
     P->nunits = (int64_t)(us.size() / 2);
-    // the FP32 matrix-core kernel takes one-step units only
-    for (int64_t u = P->unit_split; P->fp32 && u < P->nunits; ++u)
+    // the chunks are one-step units
+    for (int64_t u = P->unit_split; u < P->nunits; ++u)
       if (us[2 * u + 1] - us[2 * u] != 1) {
-        set_last_error("internal: FP32 M2L unit with more than one step");
+        set_last_error("internal: M2L unit with more than one step");
         return FMMLM_EUNSUPPORTED;
       }
     // operator tables must fit a budget (FP64 + FP32 copies)

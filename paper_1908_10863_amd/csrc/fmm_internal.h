@@ -142,11 +142,11 @@ struct fmmlm_plan_s {
   int32_t *m2l_nfree = nullptr;    // [NB] number of free entries per target box
   int32_t *m2l_src = nullptr, *m2l_op = nullptr;  // op < 0 encodes mirrored source: ~op
   double* G = nullptr;             // operators [nops][ng] complex (re, im interleaved)
-  // free-space M2L as GEMMs over tiles of target boxes
+  // M2L as GEMMs over operator-major chunks (a chunk is a tile of its own)
   double* Tfree = nullptr;         // [nops][nrk][32 mrt] real-form operators (free space, then reaction)
   int nrk = 0, mrt = 0;            // padded inner dimension, rows per thread / 32
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
-  int64_t tile_grp[5] = {0};       // tile groups: free / reaction on FP64 levels, then on the others
+  int64_t tile_grp[5] = {0};       // target-tile groups (none: all zero, the chunks follow)
   int m2l_variant = 0;             // FP32 M2L tile shape picked by the autotuner
   int batch_variant = 0;           // batched FP32 M2L shape / persistence picked by the autotuner
   // M2M / L2L as GEMMs: 16 real-form operators (8 child octants up, 8 down)
