@@ -844,14 +844,14 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   }
   // ---- M2M / L2L as GEMMs over tiles of up to xl_tile_cols target boxes of one
   // level: M2M tiles hold parents (one step per child octant present, source
-  // = that child, operator = octant); L2L tiles hold children of one octant
-  // (one step, source = the parent, operator 8 + octant).  One unit per step,
-  // so an L2L tile is one unit, added with it (the GEMM adds L2L products into
-  // the children directly).
+  // = that child, operator = octant; at most 8 units a tile, summed by the
+  // kernel's block in unit order); L2L tiles hold children of one octant (one
+  // step, source = the parent, operator 8 + octant), so an L2L tile is one
+  // unit, whose product is added into the children directly.
   {
     // narrow tiles: a level's translations are few, so more and smaller blocks
     const int TBc = P->xl_tile_cols;
-    std::vector<int32_t> xop, xkind, xsrc, xmask, xus, xumask, xtuptr(1, 0), xtgt, xlev;
+    std::vector<int32_t> xop, xsrc, xus, xumask, xtuptr(1, 0), xtgt, xlev;
     auto add_tile = [&](int l, const std::vector<int32_t>& tg, const std::vector<std::vector<int32_t>>& src,
                         const std::vector<int>& ops) {
       xlev.push_back(l);
@@ -859,14 +859,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       for (size_t k = 0; k < ops.size(); ++k) {
         const int32_t a = (int32_t)xop.size();
         xop.push_back(ops[k]);
-        xkind.push_back((int32_t)(FMMLM_FREE | FMMLM_REACTION));
         uint32_t msk = 0;
         for (int c = 0; c < TBc; ++c) {
           const int32_t v = c < (int)src[k].size() ? src[k][c] : -1;
           xsrc.push_back(v);
           if (v >= 0) msk |= 1u << (c >> 3);
         }
-        xmask.push_back((int32_t)msk);
         xus.push_back(a);
         xus.push_back(a + 1);
         xumask.push_back((int32_t)msk);
@@ -948,10 +946,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     int rc0;
 #define UPX(field, vec) if ((rc0 = dev_upload(P, &P->field, vec, st))) return rc0
-    UPX(xl_step_op, xop); UPX(xl_step_kind, xkind); UPX(xl_step_src, xsrc); UPX(xl_step_mask, xmask);
+    UPX(xl_step_op, xop); UPX(xl_step_src, xsrc);
     UPX(xl_unit_s, xus); UPX(xl_unit_mask, xumask); UPX(xl_tile_unit_ptr, xtuptr); UPX(xl_tile_tgt, xtgt);
 #undef UPX
-    if ((rc0 = dev_alloc(P, &P->Wxl, (size_t)std::max<int64_t>(P->xl_units, 1) * TBc * 32 * P->mrt))) return rc0;
   }
   // ---- P2P CSR over leaves
   std::vector<int32_t> pptr(P->nleaves + 1, 0), psrc;

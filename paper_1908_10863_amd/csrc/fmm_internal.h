@@ -155,9 +155,8 @@ struct fmmlm_plan_s {
   std::vector<std::array<int64_t, 4>> xl_m2m, xl_l2l;
   std::vector<char> xl_need_m2m, xl_need_l2l;  // per level: the translation into it is needed
   int64_t xl_units = 0;
-  int32_t *xl_step_op = nullptr, *xl_step_kind = nullptr, *xl_step_src = nullptr, *xl_step_mask = nullptr;
+  int32_t *xl_step_op = nullptr, *xl_step_src = nullptr;
   int32_t *xl_unit_s = nullptr, *xl_unit_mask = nullptr, *xl_tile_unit_ptr = nullptr, *xl_tile_tgt = nullptr;
-  double* Wxl = nullptr;           // [xl_units][xl_tile_cols][32 mrt] partial products
   int xl_tile_cols = 32;           // target boxes per translation tile
   int32_t* sp_boxes = nullptr;     // target boxes of the sparse top levels (no tiles there)
   // their work items (sparse box, first entry, end entry), per box a run of
