@@ -705,7 +705,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
   }
   // ---- M2L steps: the top levels (few boxes, many distinct operators) go to
   // the sparse FP64 kernel, the levels below them operator-major: chunks of up
-  // to tile_cols pairs of one operator, each a tile of its own with one step
+  // to tile_cols targets of a group of operators, each a tile of its own
   std::vector<int32_t> tptr(1, 0), ttgt, tlev, sop, skind, ssrc, smask, us, umask, tuptr;
   {
     {
@@ -755,12 +755,16 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     for (int grp = 0; grp <= 4; ++grp) P->tile_grp[grp] = 0;  // no target tiles (M2L is operator-major)
     // Levels below the sparse ones: operator-major chunks (FP32 products on the
-    // FP32 form's matrix-core kernel, FP64 ones on the FP64 tile GEMM).  All
-    // pairs of one operator (in box units a free-space operator serves every
-    // level) are taken TBc at a time as one step (a tile of its own, one unit);
-    // a target appears at most once per operator, so a chunk's columns are
-    // distinct targets.  Each target's outputs are then summed over its slots
-    // (unit, column) in operator order by m2l_slot_reduce_kernel.
+    // FP32 form's matrix-core kernel, FP64 ones on the FP64 tile GEMM).  The
+    // operators are taken kM2LGroupOps at a time in operator order (in box units
+    // a free-space operator serves every level); the targets that every
+    // operator of the group reaches are taken TBc at a time as one chunk whose
+    // steps are the group's operators, each with its own sources, so the chunk
+    // stores one partial sum per target for all of them.  The rest of each
+    // operator's pairs form one-step chunks.  A target appears at most once per
+    // operator, so a chunk's columns are distinct targets.  Each target's outputs
+    // are then summed over its slots (chunk, column) in chunk order by
+    // m2l_slot_reduce_kernel.
     {
       std::vector<std::array<int32_t, 3>> pr;  // (operator, target, source)
       for (int l = ksp; l <= P->maxlev; ++l)
@@ -768,31 +772,92 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
           for (int32_t e = mptr[b]; e < mptr[b + 1]; ++e)
             pr.push_back({(mop[e] >= 0) ? mop[e] : ~mop[e], (int32_t)b, msrc[e]});
       std::sort(pr.begin(), pr.end());
-      std::vector<std::vector<int32_t>> tslots(P->NB);
+      std::vector<std::pair<size_t, size_t>> oprng;  // each operator's pairs [i0, i1) in pr
       for (size_t i0 = 0; i0 < pr.size();) {
         size_t i1 = i0;
         while (i1 < pr.size() && pr[i1][0] == pr[i0][0]) ++i1;
-        const int op = pr[i0][0];
-        for (size_t c0 = i0; c0 < i1; c0 += TBc) {
-          const size_t nc_ = std::min<size_t>(TBc, i1 - c0);
-          const int32_t unit = (int32_t)tlev.size();  // one unit per chunk
-          tlev.push_back(B.boxes[pr[c0][1]].level);
-          uint32_t msk = 0;
-          for (size_t c = 0; c < (size_t)TBc; ++c) {
-            const bool on = c < nc_;
-            ttgt.push_back(on ? pr[c0 + c][1] : -1);
-            ssrc.push_back(on ? pr[c0 + c][2] : -1);
-            if (on) {
-              msk |= 1u << (c >> 3);
-              tslots[pr[c0 + c][1]].push_back(unit * TBc + (int32_t)c);
+        oprng.push_back({i0, i1});
+        i0 = i1;
+      }
+      std::vector<std::vector<int32_t>> tslots(P->NB);
+      std::vector<char> done(pr.size(), 0);
+      std::vector<int32_t> hits(P->NB, 0);
+      // one chunk: columns c < nc_ hold targets tg[c]; step k applies operator
+      // ops[k] to sources src[k][c]
+      auto add_chunk = [&](const std::vector<int32_t>& ops, const std::vector<int32_t>& tg,
+                           const std::vector<std::vector<int32_t>>& src) {
+        const int32_t unit = (int32_t)tlev.size();  // one unit per chunk
+        tlev.push_back(B.boxes[tg[0]].level);
+        uint32_t msk = 0;
+        for (size_t c = 0; c < (size_t)TBc; ++c) {
+          const bool on = c < tg.size();
+          ttgt.push_back(on ? tg[c] : -1);
+          if (on) {
+            msk |= 1u << (c >> 3);
+            tslots[tg[c]].push_back(unit * TBc + (int32_t)c);
+          }
+        }
+        for (size_t k = 0; k < ops.size(); ++k) {
+          for (size_t c = 0; c < (size_t)TBc; ++c) ssrc.push_back(c < tg.size() ? src[k][c] : -1);
+          sop.push_back(ops[k]);
+          skind.push_back(ops[k] < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
+          smask.push_back((int32_t)msk);
+        }
+        tptr.push_back((int32_t)sop.size());
+      };
+      for (size_t g0 = 0; g0 < oprng.size(); g0 += kM2LGroupOps) {
+        const size_t g1 = std::min(oprng.size(), g0 + kM2LGroupOps);
+        if (g1 - g0 > 1) {
+          for (size_t o = g0; o < g1; ++o)
+            for (size_t i = oprng[o].first; i < oprng[o].second; ++i) ++hits[pr[i][1]];
+          // pairs of the group's targets common to all its operators, per
+          // operator in target order (each list is sorted by target)
+          std::vector<std::vector<size_t>> com(g1 - g0);
+          for (size_t o = g0; o < g1; ++o)
+            for (size_t i = oprng[o].first; i < oprng[o].second; ++i)
+              if (hits[pr[i][1]] == (int32_t)(g1 - g0)) com[o - g0].push_back(i);
+          for (size_t o = g0; o < g1; ++o)
+            for (size_t i = oprng[o].first; i < oprng[o].second; ++i) hits[pr[i][1]] = 0;
+          const size_t ncom = com[0].size();
+          if (ncom >= (size_t)kM2LGroupMinTargets) {
+            std::vector<int32_t> ops;
+            for (size_t o = g0; o < g1; ++o) ops.push_back(pr[oprng[o].first][0]);
+            for (size_t c0 = 0; c0 < ncom; c0 += TBc) {
+              const size_t n_ = std::min<size_t>(TBc, ncom - c0);
+              std::vector<int32_t> tg(n_);
+              std::vector<std::vector<int32_t>> src(g1 - g0, std::vector<int32_t>(n_));
+              for (size_t c = 0; c < n_; ++c) {
+                tg[c] = pr[com[0][c0 + c]][1];
+                for (size_t k = 0; k < g1 - g0; ++k) {
+                  const size_t i = com[k][c0 + c];
+                  if (pr[i][1] != tg[c]) {
+                    set_last_error("internal: M2L operator group targets out of step");
+                    return FMMLM_EUNSUPPORTED;
+                  }
+                  src[k][c] = pr[i][2];
+                  done[i] = 1;
+                }
+              }
+              add_chunk(ops, tg, src);
             }
           }
-          sop.push_back(op);
-          skind.push_back(op < nfo ? (int32_t)FMMLM_FREE : (int32_t)FMMLM_REACTION);
-          smask.push_back((int32_t)msk);
-          tptr.push_back((int32_t)sop.size());
         }
-        i0 = i1;
+        // the group's other pairs, operator by operator
+        for (size_t o = g0; o < g1; ++o) {
+          std::vector<size_t> rest;
+          for (size_t i = oprng[o].first; i < oprng[o].second; ++i)
+            if (!done[i]) rest.push_back(i);
+          for (size_t c0 = 0; c0 < rest.size(); c0 += TBc) {
+            const size_t n_ = std::min<size_t>(TBc, rest.size() - c0);
+            std::vector<int32_t> tg(n_);
+            std::vector<std::vector<int32_t>> src(1, std::vector<int32_t>(n_));
+            for (size_t c = 0; c < n_; ++c) {
+              tg[c] = pr[rest[c0 + c]][1];
+              src[0][c] = pr[rest[c0 + c]][2];
+            }
+            add_chunk({pr[oprng[o].first][0]}, tg, src);
+          }
+        }
       }
       P->tile_grp[3] = P->tile_grp[4] = (int64_t)tlev.size();
       std::vector<int32_t> sbox, sptr(1, 0), slots;
@@ -812,7 +877,8 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->nsteps = (int64_t)sop.size();
     P->stats.m2l_steps = P->nsteps;
     P->stats.m2l_tile_cols = TBc;
-    // work units: one step each (the chunks); unit_split is 0 (no target tiles)
+    // work units: one per chunk (a chunk has at most kM2LGroupOps steps);
+    // unit_split is 0 (no target tiles)
     constexpr int kStepsPerUnit = 16;
     tuptr.assign(1, 0);
     for (int64_t t = 0; t < P->ntiles; ++t) {
@@ -829,12 +895,30 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     }
     if (P->ntiles == P->tile_grp[2]) P->unit_split = (int64_t)(us.size() / 2);
     P->nunits = (int64_t)(us.size() / 2);
-    // the chunks are one-step units
-    for (int64_t u = P->unit_split; u < P->nunits; ++u)
-      if (us[2 * u + 1] - us[2 * u] != 1) {
-        set_last_error("internal: M2L unit with more than one step");
-        return FMMLM_EUNSUPPORTED;
+    // the chunk units in 8 contiguous ranges of about equal steps, one per XCD
+    // (contiguous, so that the chunks of one operator share an XCD's L2)
+    {
+      const int64_t u0 = P->unit_split, n = P->nunits - u0;
+      const int64_t tot = n > 0 ? (int64_t)us[2 * (P->nunits - 1) + 1] - us[2 * u0] : 0;
+      int64_t u = 0, acc = 0;
+      P->m2l_xcd.off[0] = 0;
+      P->m2l_xcd_len = 0;
+      for (int x = 1; x <= 8; ++x) {
+        const int64_t goal = tot * x / 8;
+        while (u < n && acc + (us[2 * (u0 + u) + 1] - us[2 * (u0 + u)]) <= goal) {
+          acc += us[2 * (u0 + u) + 1] - us[2 * (u0 + u)];
+          ++u;
+        }
+        if (x == 8) u = n;
+        P->m2l_xcd.off[x] = (int32_t)u;
+        P->m2l_xcd_len = std::max<int32_t>(P->m2l_xcd_len, P->m2l_xcd.off[x] - P->m2l_xcd.off[x - 1]);
       }
+    }
+    // each chunk is one unit (the slots index units by chunk)
+    if (P->nunits != P->ntiles || P->unit_split != 0) {
+      set_last_error("internal: M2L chunks and units differ");
+      return FMMLM_EUNSUPPORTED;
+    }
     // operator tables must fit a budget (FP64 + FP32 copies)
     const double tbytes = (double)P->nops * P->nrk * 32.0 * P->mrt * (P->fp32 ? 12.0 : 8.0);
     if (tbytes > 32.0 * (1 << 30)) {

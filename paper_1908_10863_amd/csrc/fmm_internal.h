@@ -27,6 +27,17 @@ constexpr int kRPUnitRows = 8;
 // a lane (8 in FP32, 4 in FP64)
 constexpr int kPLUnitTargetsF32 = 128;
 constexpr int kPLUnitTargetsF64 = 64;
+// operator-major M2L: operators grouped into one chunk's steps, and the
+// fewest targets common to a group's operators that make grouped chunks
+constexpr int kM2LGroupOps = 2;
+constexpr int kM2LGroupMinTargets = 64;
+
+// unit ranges of the FP32 M2L launch per XCD (the 8 XCDs take blocks in turn):
+// XCD x runs units [off[x], off[x + 1]) of the launch, ranges of about equal
+// steps
+struct XcdSplit {
+  int32_t off[9];
+};
 
 // ---- small complex type (device and host) ------------------------------------
 struct cplx {
@@ -148,6 +159,8 @@ struct fmmlm_plan_s {
   int tile_cols = 64;              // target boxes per tile (128 when mrt <= 4)
   int64_t tile_grp[5] = {0};       // target-tile groups (none: all zero, the chunks follow)
   int m2l_variant = 0;             // FP32 M2L tile shape picked by the autotuner
+  fmmlm::XcdSplit m2l_xcd{};        // FP32 M2L: the chunk units' ranges per XCD
+  int32_t m2l_xcd_len = 0;          //   ... and the longest range (blocks per XCD)
   int batch_variant = 0;           // batched FP32 M2L shape / persistence picked by the autotuner
   // M2M / L2L as GEMMs: 16 real-form operators (8 child octants up, 8 down)
   // and their own tiles; per level (first tile, first unit, end tile, end unit)
@@ -176,7 +189,7 @@ struct fmmlm_plan_s {
   int32_t *unit_mask = nullptr;    // [nunits] column groups of 8 that the unit's partial holds
   int32_t *tile_unit_ptr = nullptr;// [ntiles + 1]
   double* Wm2l = nullptr;          // [nunits][tile_cols][32 mrt] partial products (FP64 form)
-  float* W32m = nullptr;           // the same in FP32 (FP32 form: single-step units)
+  float* W32m = nullptr;           // the same in FP32 (FP32 form)
   // FP32 form
   bool fp32 = false;
   float* Tfree32 = nullptr;        // FP32 copy of Tfree
