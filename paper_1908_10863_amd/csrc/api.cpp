@@ -779,6 +779,25 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
         oprng.push_back({i0, i1});
         i0 = i1;
       }
+      // free-space operators in classes of equal reach: a box meets offset
+      // component +3 (or -3) along an axis only from one child position of its
+      // parent, so operators of one class reach the same targets (the boundary
+      // aside) and group well; reaction operators keep their order after them
+      {
+        auto cls = [&](int op) {
+          if (op >= nfo) return 27;
+          int c = 0;
+          for (int a = 0; a < 3; ++a) {
+            const int v = B.free_off[3 * op + a];
+            c = 3 * c + (v >= 3 ? 1 : (v <= -3 ? 2 : 0));
+          }
+          return c;
+        };
+        std::stable_sort(oprng.begin(), oprng.end(), [&](const std::pair<size_t, size_t>& x,
+                                                         const std::pair<size_t, size_t>& y) {
+          return cls(pr[x.first][0]) < cls(pr[y.first][0]);
+        });
+      }
       std::vector<std::vector<int32_t>> tslots(P->NB);
       std::vector<char> done(pr.size(), 0);
       std::vector<int32_t> hits(P->NB, 0);

@@ -29,7 +29,7 @@ constexpr int kPLUnitTargetsF32 = 128;
 constexpr int kPLUnitTargetsF64 = 64;
 // operator-major M2L: operators grouped into one chunk's steps, and the
 // fewest targets common to a group's operators that make grouped chunks
-constexpr int kM2LGroupOps = 2;
+constexpr int kM2LGroupOps = 4;
 constexpr int kM2LGroupMinTargets = 64;
 
 // unit ranges of the FP32 M2L launch per XCD (the 8 XCDs take blocks in turn):
