@@ -773,20 +773,30 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
             pr.push_back({(mop[e] >= 0) ? mop[e] : ~mop[e], (int32_t)b, msrc[e]});
       std::sort(pr.begin(), pr.end());
       std::vector<std::pair<size_t, size_t>> oprng;  // each operator's pairs [i0, i1) in pr
+      std::vector<uint64_t> opclass;                 // ... and its class (after the sort below)
       for (size_t i0 = 0; i0 < pr.size();) {
         size_t i1 = i0;
         while (i1 < pr.size() && pr[i1][0] == pr[i0][0]) ++i1;
         oprng.push_back({i0, i1});
         i0 = i1;
       }
-      // free-space operators in classes of equal reach: a box meets offset
-      // component +3 (or -3) along an axis only from one child position of its
-      // parent, so operators of one class reach the same targets (the boundary
-      // aside) and group well; reaction operators keep their order after them
+      // operators in classes that reach the same targets, so that a group's
+      // operators share most of them.  Free space: a box meets offset component
+      // +3 (or -3) along an axis only from one child position of its parent, so
+      // the operators of one such class reach the same targets (the boundary
+      // aside).  Reaction operators (after the free ones) by level, offset and
+      // component: the components of one offset often hold the same pairs.
       {
-        auto cls = [&](int op) {
-          if (op >= nfo) return 27;
-          int c = 0;
+        std::vector<uint64_t> rkey((size_t)(P->nops - nfo), 0);
+        for (const auto& kv : B.reac_op_id) {
+          const int comp = std::get<0>(kv.first), lvl = std::get<1>(kv.first);
+          const int dx = std::get<2>(kv.first), dy = std::get<3>(kv.first), dz = std::get<4>(kv.first);
+          rkey[kv.second] = ((uint64_t)lvl << 40) | ((uint64_t)(dz & 0xff) << 32) | ((uint64_t)(dx & 0xff) << 24) |
+                            ((uint64_t)(dy & 0xff) << 16) | (uint64_t)(comp & 0xffff);
+        }
+        auto key = [&](int op) -> uint64_t {
+          if (op >= nfo) return (uint64_t(1) << 63) | rkey[op - nfo];
+          uint64_t c = 0;
           for (int a = 0; a < 3; ++a) {
             const int v = B.free_off[3 * op + a];
             c = 3 * c + (v >= 3 ? 1 : (v <= -3 ? 2 : 0));
@@ -795,8 +805,13 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
         };
         std::stable_sort(oprng.begin(), oprng.end(), [&](const std::pair<size_t, size_t>& x,
                                                          const std::pair<size_t, size_t>& y) {
-          return cls(pr[x.first][0]) < cls(pr[y.first][0]);
+          return key(pr[x.first][0]) < key(pr[y.first][0]);
         });
+        // a group holds operators of one class (reaction: one offset)
+        for (const auto& r : oprng) {
+          const uint64_t k = key(pr[r.first][0]);
+          opclass.push_back((k >> 63) ? (k & ~(uint64_t)0xffff) : k);
+        }
       }
       std::vector<std::vector<int32_t>> tslots(P->NB);
       std::vector<char> done(pr.size(), 0);
@@ -824,8 +839,9 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
         }
         tptr.push_back((int32_t)sop.size());
       };
-      for (size_t g0 = 0; g0 < oprng.size(); g0 += kM2LGroupOps) {
-        const size_t g1 = std::min(oprng.size(), g0 + kM2LGroupOps);
+      for (size_t g0 = 0, g1 = 0; g0 < oprng.size(); g0 = g1) {
+        g1 = g0 + 1;
+        while (g1 < oprng.size() && g1 - g0 < (size_t)kM2LGroupOps && opclass[g1] == opclass[g0]) ++g1;
         if (g1 - g0 > 1) {
           for (size_t o = g0; o < g1; ++o)
             for (size_t i = oprng[o].first; i < oprng[o].second; ++i) ++hits[pr[i][1]];
