@@ -1401,6 +1401,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     hipFree(ds);
     hipFree(dc);
     if (rc) return rc;
+    // the FP32 form's single-vector reaction P2P reads the values rounded to
+    // FP32 (half the bytes of that HBM-bound stage; sums stay FP64)
+    if (P->fp32) {
+      if ((rc = dev_alloc(P, &P->rp_val32, (size_t)npairs))) return rc;
+      if ((rc = gpu_round_f32(P->rp_val, npairs, P->rp_val32, st))) return rc;
+    }
   }
   // ---- workspace (G = min(max_rhs, 64) vectors per pass)
   P->gmax = std::min(P->opts.max_rhs, 64);

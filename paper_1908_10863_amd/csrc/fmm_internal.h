@@ -245,6 +245,7 @@ struct fmmlm_plan_s {
   int32_t *rp_src = nullptr;       // [2 * entries] (start, count)
   int64_t *rp_voff = nullptr;      // [entries] value offset
   double *rp_val = nullptr;        // kernel values, row-major per entry (targets x sources)
+  float* rp_val32 = nullptr;        // FP32 form: the same rounded to FP32 (single-vector reaction P2P)
   int32_t *rp_row = nullptr;       // [entries] first partial-sum slot of the entry's target rows
   int32_t *rp_units = nullptr;     // [3 * n_rp_units] (entry, first row, target count)
   int64_t n_rp_units = 0;
@@ -398,6 +399,8 @@ int gpu_tune_eval(fmmlm_plan_s* P, hipStream_t st);
 constexpr int kM2LVariants = 6;  // FP32 M2L tile shapes the autotuner tries
 constexpr int kBatchShapes = 5;  // batched FP32 M2L tile shapes (each also persistent)
 int gpu_tune_batch(fmmlm_plan_s* P, hipStream_t st);
+// b[i] = (float)a[i], i < n (the FP32 form's copy of the reaction near-field values)
+int gpu_round_f32(const double* a, int64_t n, float* b, hipStream_t st);
 int gpu_build_fp32(fmmlm_plan_s* P, hipStream_t st);
 int gpu_eval_batch(fmmlm_plan_s* P, int g, const double* q, int64_t ldq, double* phi, int64_t ldphi,
                    uint32_t parts, hipStream_t st, hipEvent_t* ev);
