@@ -269,9 +269,10 @@ typedef struct {
                                     |difference of S^N I_{N,M}|, R1 = |(rho, z + zinf)| (the error
                                     relative to the interaction 1/R1 that the operator carries).
                                     Above 1e-5 the plan rejects the form (surrogate_rejected) */
-  int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one tile) ... */
-  int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the tiles is
-                                    (m2l_free_pairs + m2l_reaction_pairs) / (steps * cols) */
+  int64_t m2l_steps;           /* M2L GEMM steps (one operator applied to one chunk's sources) ... */
+  int32_t m2l_tile_cols;       /*   ... of this many target columns: the fill of the steps is
+                                    (m2l_free_pairs + m2l_reaction_pairs - m2l_top_pairs)
+                                    / (steps * cols) */
   int32_t m2l_variant;         /* FP32 form: M2L tile shape picked by the plan's autotuner (see m2l_eval_ms) */
   int64_t m2l_top_pairs;       /* M2L pairs on the top levels (fp64_top_levels), run by the
                                     sparse FP64 kernel in the "M2L top" stage */
@@ -306,6 +307,10 @@ typedef struct {
                                   p2p_reserve_ms; it bounds the P2P blocks a CU holds and leaves
                                   room for far-field blocks beside them */
   double p2p_reserve_ms[3];    /*   ... whole-evaluation times with 28672, 40960 and 0 bytes */
+  int64_t m2l_chunks;          /* M2L chunks below the top levels: each holds up to m2l_tile_cols
+                                  targets and one step per operator of its group (up to 4
+                                  operators that reach the same targets), and stores one partial
+                                  sum per target for all its steps */
 } fmmlm_stats;
 
 int fmm_layered_plan_stats(fmmlm_plan_t plan, fmmlm_stats* out);

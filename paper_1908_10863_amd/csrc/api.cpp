@@ -911,6 +911,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
     P->ntiles = (int64_t)tlev.size();
     P->nsteps = (int64_t)sop.size();
     P->stats.m2l_steps = P->nsteps;
+    P->stats.m2l_chunks = P->ntiles;
     P->stats.m2l_tile_cols = TBc;
     // work units: one per chunk (a chunk has at most kM2LGroupOps steps);
     // unit_split is 0 (no target tiles)

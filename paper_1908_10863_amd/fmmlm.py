@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("surrogate_rejected", ctypes.c_int32), ("batch_variant_ms", ctypes.c_double * 10),
                 ("m2l_eval_ms", ctypes.c_double * 6), ("p2p_split_ms", ctypes.c_double * 5),
                 ("p2p_split_pct", ctypes.c_int32), ("batch_min_rhs", ctypes.c_int32),
-                ("p2p_lds_reserve", ctypes.c_int32), ("p2p_reserve_ms", ctypes.c_double * 3)]
+                ("p2p_lds_reserve", ctypes.c_int32), ("p2p_reserve_ms", ctypes.c_double * 3),
+                ("m2l_chunks", ctypes.c_int64)]
 
 
 EXPORTS = ["fmmlm_default_opts", "fmm_layered_plan", "fmm_layered_eval", "fmm_layered_destroy",

@@ -156,3 +156,35 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fmmlm, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         fmmlm.lib()
+
+
+_CTYPE = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64,
+          "double": ctypes.c_double, "float": ctypes.c_float, "fmmlm_surrogate_t": ctypes.c_void_p}
+
+
+def _header_struct(name):
+    """(field, ctypes type) of `typedef struct {...} name;` in include/fmmlm.h, in order."""
+    src = open(os.path.join(ROOT, "include", "fmmlm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
+    out = []
+    for ty, names in re.findall(r"(\w+)\s+([^;]+);", body):  # "type a, b[3];"
+        t = _CTYPE[ty]
+        for fld, n in re.findall(r"(\w+)\s*(?:\[(\d+)\])?", names):
+            out.append((fld, t * int(n) if n else t))
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("fmmlm_opts", "Opts"), ("fmmlm_stats", "Stats"),
+                                          ("fmmlm_solve_opts", "SolveOpts"), ("fmmlm_solve_info", "SolveInfo"),
+                                          ("fmmlm_train_opts", "TrainOpts"),
+                                          ("fmmlm_train_report", "TrainReport")])
+def test_binding_structs_match_the_header(cname, pyname):
+    """Every struct the binding passes across the boundary has the header's fields, in the
+    header's order and with its types, so offsets and size agree with the C layout."""
+    from paper_1908_10863_amd import fmmlm
+    hdr = _header_struct(cname)
+    py = getattr(fmmlm, pyname)._fields_
+    assert [f for f, _ in py] == [f for f, _ in hdr], cname
+    for (f, tp), (_, th) in zip(py, hdr):
+        assert ctypes.sizeof(tp) == ctypes.sizeof(th) and getattr(tp, "_type_", tp) == getattr(th, "_type_", th), (cname, f)

@@ -151,6 +151,36 @@ def test_fp32_full_size_sampled(dev, F, oracle_mod):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_m2l_operator_groups(dev, F, oracle_mod, precision):
+    """Below the top levels the M2L runs in chunks of up to four operators that reach the
+    same targets, one step per operator and one partial per target for all of a chunk's
+    steps.  On a uniform workload with interior boxes most pairs are grouped (fewer
+    chunks than steps, at most four steps a chunk), every pair sits in one step column
+    (steps x columns >= pairs below the top levels), and the result meets the 1e-5 bar
+    against the direct sum on sampled targets in both forms."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say(f"M2L operator groups, precision={precision}")
+    w = W.config(2, n=200000, seed=5)
+    plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=10, leaf_cap=64,
+                  precision=precision, mac_d2=4)
+    st = plan.stats()
+    pairs = st["m2l_free_pairs"] + st["m2l_reaction_pairs"] - st["m2l_top_pairs"]
+    _say(f"  chunks {st['m2l_chunks']} steps {st['m2l_steps']} pairs {pairs}")
+    assert 0 < st["m2l_chunks"] < st["m2l_steps"] <= 4 * st["m2l_chunks"]
+    assert st["m2l_steps"] >= 1.5 * st["m2l_chunks"]  # most pairs grouped
+    assert pairs <= st["m2l_steps"] * st["m2l_tile_cols"]
+    q = torch.tensor(w["q"][0], dtype=torch.float64, device=dev)
+    phi = plan.eval(q).cpu().numpy()
+    plan.close()
+    t = np.sort(np.random.default_rng(55).choice(len(w["x"]), 128, replace=False))
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0], targets=t)
+    e = relerr(phi[t], ref)
+    _say(f"  rel L2 {e:.3e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_streams_and_tuning_do_not_change_results(dev, F, precision):
     """An unprofiled evaluation runs the near field and the sparse top levels on
     their own streams, with part of the free P2P after the main M2L and extra LDS
