@@ -218,6 +218,32 @@ def test_spectral_convergence_in_p(dev, F, oracle_mod):
     assert errs[-1] < 1e-6
 
 
+def test_every_order(dev, F, oracle_mod):
+    """Every truncation order p = 1..16 (the kernels with the order fixed at compile time,
+    P2M and L2P, have one instantiation each, and the M2L tiles one row count per few
+    orders): the FP64 form's error does not grow from one order to the next and is
+    below 1e-8 at p = 16; the FP32 form stays within its rounding floor of the FP64 form."""
+    import torch
+    from paper_1908_10863_amd import workloads as W
+    _say("every order p = 1..16")
+    w = W.config(0)
+    ref = oracle_mod.potential(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], w["q"][0])
+    q = torch.tensor(w["q"][0], dtype=torch.float64, device=dev)
+    e64, e32 = [], []
+    for p in range(1, 17):
+        for prec, out in ((F.FMMLM_FP64, e64), (F.FMMLM_FP32_COMPENSATED, e32)):
+            plan = F.Plan(w["d"], w["eps"], w["x"], w["y"], w["z"], w["layer"], p=p,
+                          leaf_cap=w["leaf_cap"], precision=prec)
+            out.append(relerr(plan.eval(q).cpu().numpy(), ref))
+            plan.close()
+        _say(f"  p={p:2d} fp64 {e64[-1]:.2e} fp32 {e32[-1]:.2e}")
+    for p in range(2, 17):
+        assert e64[p - 1] <= 1.5 * e64[p - 2] + 1e-12, p
+    assert e64[-1] < 1e-8
+    for a, b in zip(e64, e32):
+        assert b <= a + 3e-6
+
+
 def test_largest_order_p16(dev, F, oracle_mod):
     """The largest truncation order (p = 16, FP64 form, default MAC) against the full
     direct sum: more accurate than p = 12's 1e-7 bound."""
