@@ -842,7 +842,12 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
       for (size_t g0 = 0, g1 = 0; g0 < oprng.size(); g0 = g1) {
         g1 = g0 + 1;
         while (g1 < oprng.size() && g1 - g0 < (size_t)kM2LGroupOps && opclass[g1] == opclass[g0]) ++g1;
-        if (g1 - g0 > 1) {
+        // (a group whose operator reaches one target twice is not grouped)
+        bool distinct = true;
+        for (size_t o = g0; o < g1 && distinct; ++o)
+          for (size_t i = oprng[o].first + 1; i < oprng[o].second; ++i)
+            if (pr[i][1] == pr[i - 1][1]) distinct = false;
+        if (g1 - g0 > 1 && distinct) {
           for (size_t o = g0; o < g1; ++o)
             for (size_t i = oprng[o].first; i < oprng[o].second; ++i) ++hits[pr[i][1]];
           // pairs of the group's targets common to all its operators, per
