@@ -1015,7 +1015,7 @@ int build_plan(fmmlm_plan_s* P, const std::vector<double>& X, const std::vector<
           const HBox& bx = B.boxes[tg[c]];
           for (int k = 0; k < bx.nchild; ++k) src[octant(bx.child0 + k)][c] = bx.child0 + k;
         }
-        std::vector<int> ops;
+        std::vector<int> ops;  // at most 8 (the translation kernel sums a tile's units in one block)
         std::vector<std::vector<int32_t>> used;
         for (int o = 0; o < 8; ++o)
           if (std::any_of(src[o].begin(), src[o].end(), [](int32_t v) { return v >= 0; })) {
