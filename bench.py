@@ -287,14 +287,20 @@ def _learned_form(fmmlm, workloads, oracle, dev, steps):
     return res
 
 
+# stages on the matrix cores (the M2L GEMMs and the translation GEMMs); the FP32 form runs
+# only its main M2L and its free P2P in FP32, every other stage in FP64
+MFMA_STAGES = ("m2l", "m2m", "l2l")
+FP32_STAGES = ("m2l", "p2p_free")
+
+
 def stage_roofline(st, p, stage, ms, fp32, rhs=1):
     """Roofline of one stage's launch: algorithmic flops over its average time, against the
-    published peak of the arithmetic that runs it (FP32 form: FP32 vector / matrix 157.3
-    TFLOP/s; FP64 form: FP64 vector / matrix 78.6 TFLOP/s)."""
+    published peak of the arithmetic that runs it (FP32 vector / matrix 157.3 TFLOP/s for
+    the FP32 form's main M2L and free P2P; FP64 vector / matrix 78.6 TFLOP/s otherwise)."""
     flops = stage_flops(st, p, stage, rhs)
     achieved = flops / (ms * 1e-3) / 1e12
-    peak = (PEAK_FP32 if fp32 else PEAK_FP64) / 1e12
-    bound = "mfma" if stage == "m2l" else "alu"
+    peak = (PEAK_FP32 if (fp32 and stage in FP32_STAGES) else PEAK_FP64) / 1e12
+    bound = "mfma" if stage in MFMA_STAGES else "alu"
     return {"bound": bound, "stage": stage, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "flops_per_launch": flops, "avg_ms": ms}
 
